@@ -1,0 +1,296 @@
+"""Pins for the CPU oracle: checks against facts fixed by the paper and by mathematics.
+
+Each pin takes an ``Oracle`` and raises ``AssertionError`` on a mismatch.  The
+same pins run against the real oracle (tests/test_oracle.py) and against
+mutated copies of it (tests/test_oracle_mutants.py), which shows that a
+plausible mistake anywhere in the oracle fails at least one of them.
+
+Sources of truth (none is the oracle itself):
+  P1  one-qubit closed forms of u(phi) = cos(phi/2) I - i sin(phi/2) P   (Sec. 3.3)
+  P2  a two-qubit closed form with CZ, and its three derivatives          (Sec. 3.1)
+  P3  all variational angles zero: <Z_i> = cos x_i, dL/dx_i = -g_i sin x_i
+  P4  norm preservation of every gate sequence
+  P5  dense 2^n x 2^n products of Kronecker-embedded gates (qubit 0 rightmost)
+  P6  parameter-shift rule, exact for exp(-i phi P / 2)                    (Sec. 1)
+  P7  un-apply backward vs store-all backward vs central finite differences (Sec. 2.2)
+  P9  Pauli-string expectation vs the dense Pauli product                 (App. B.2)
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from paper_2603_02804_amd.workloads import CZ, RX, RY, RZ, hea_gates, pauli_string, z_observables
+
+I2 = np.eye(2, dtype=np.complex128)
+PX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+PY = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+PZ = np.array([[1, 0], [0, -1]], dtype=np.complex128)
+
+
+def _g(kind, q0, q1=-1, t=-1, f=-1):
+    return (kind, q0, q1, t, f)
+
+
+def _gates(rows):
+    return np.asarray(rows, dtype=np.int32).reshape(-1, 5)
+
+
+def _E(orc, n, gates, theta, x, obs):
+    xm = np.asarray([o[0] for o in obs], dtype=np.uint64)
+    zm = np.asarray([o[1] for o in obs], dtype=np.uint64)
+    return orc.forward(n, gates, theta, x, xm, zm)
+
+
+# ---------------------------------------------------------------- P1
+def pin_p1_single_qubit(orc):
+    """RY(phi)|0>: <Z>=cos phi, <X>=sin phi.  RX(phi)|0>: <Z>=cos phi, <Y>=-sin phi.
+    RZ(phi) after RY(a)|0> turns the Bloch vector about z: <X>=sin a cos phi,
+    <Y>=sin a sin phi, <Z>=cos a.  u(phi) u(-phi) = I.  The adjoint backward of a
+    single RX or RY gives d<Z>/dphi = -sin phi."""
+    X, Y, Z = (1, 0), (1, 1), (0, 1)
+    for phi in (0.3, 1.1, -2.4, 3.0):
+        E = _E(orc, 1, _gates([_g(RY, 0, t=0)]), [phi], np.zeros((1, 0)), [Z, X, Y])[0]
+        np.testing.assert_allclose(E, [math.cos(phi), math.sin(phi), 0.0], atol=1e-13)
+        E = _E(orc, 1, _gates([_g(RX, 0, t=0)]), [phi], np.zeros((1, 0)), [Z, X, Y])[0]
+        np.testing.assert_allclose(E, [math.cos(phi), 0.0, -math.sin(phi)], atol=1e-13)
+        a = 0.7
+        E = _E(orc, 1, _gates([_g(RY, 0, t=0), _g(RZ, 0, t=1)]), [a, phi], np.zeros((1, 0)), [Z, X, Y])[0]
+        np.testing.assert_allclose(E, [math.cos(a), math.sin(a) * math.cos(phi), math.sin(a) * math.sin(phi)],
+                                   atol=1e-13)
+        # u(phi) u(-phi) = I for each Pauli: the state returns to RY(a)|0>
+        for k in (RX, RY, RZ):
+            E = _E(orc, 1, _gates([_g(RY, 0, t=0), _g(k, 0, t=1), _g(k, 0, t=2)]), [a, phi, -phi],
+                   np.zeros((1, 0)), [Z, X, Y])[0]
+            np.testing.assert_allclose(E, [math.cos(a), math.sin(a), 0.0], atol=1e-13)
+        for k in (RX, RY):
+            gates = _gates([_g(k, 0, t=0)])
+            _, dth, _ = orc.backward(1, gates, [phi], np.zeros((1, 0)), [0], [1], [[1.0]])
+            np.testing.assert_allclose(dth, [-math.sin(phi)], atol=1e-13)
+
+
+# ---------------------------------------------------------------- P2
+def pin_p2_two_qubit(orc):
+    """RY(a) q0, RY(b) q1, CZ(0,1), RY(c) q0:  <Z_0> = cos a cos c - sin a sin c cos b.
+    The angles a and b come from the input vector x, c from theta, so both gradient
+    outputs are checked against the closed-form derivatives."""
+    rng = np.random.default_rng(12)
+    for _ in range(4):
+        a, b, c = rng.uniform(-math.pi, math.pi, size=3)
+        gates = _gates([_g(RY, 0, f=0), _g(RY, 1, f=1), _g(CZ, 0, 1), _g(RY, 0, t=0)])
+        x = np.array([[a, b]])
+        E, dth, dx = orc.backward(2, gates, [c], x, [0], [1], [[1.0]])
+        ref = math.cos(a) * math.cos(c) - math.sin(a) * math.sin(c) * math.cos(b)
+        np.testing.assert_allclose(E[0, 0], ref, atol=1e-13)
+        da = -math.sin(a) * math.cos(c) - math.cos(a) * math.sin(c) * math.cos(b)
+        db = math.sin(a) * math.sin(c) * math.sin(b)
+        dc = -math.cos(a) * math.sin(c) - math.sin(a) * math.cos(c) * math.cos(b)
+        np.testing.assert_allclose(dx[0], [da, db], atol=1e-13)
+        np.testing.assert_allclose(dth, [dc], atol=1e-13)
+        # the CZ order (control/target) does not matter
+        gates2 = _gates([_g(RY, 0, f=0), _g(RY, 1, f=1), _g(CZ, 1, 0), _g(RY, 0, t=0)])
+        E2 = orc.forward(2, gates2, [c], x, [0], [1])
+        np.testing.assert_allclose(E2[0, 0], ref, atol=1e-13)
+
+
+# ---------------------------------------------------------------- P3
+def pin_p3_zero_angles(orc, n=7, layers=3):
+    """All variational angles zero: the HEA reduces to the encoding plus diagonal
+    gates, so <Z_i> = cos x_i and dL/dx_i = -g_i sin x_i (L = sum_i g_i <Z_i>)."""
+    for rots in (("RY", "RZ"), ("RX", "RY", "RZ")):
+        gates = hea_gates(n, layers, rots)
+        P = layers * len(rots) * n
+        rng = np.random.default_rng(3)
+        x = rng.uniform(-math.pi, math.pi, size=(3, n))
+        g = rng.normal(size=(3, n))
+        xm, zm = z_observables(range(n))
+        E, dth, dx = orc.backward(n, gates, np.zeros(P), x, xm, zm, g)
+        np.testing.assert_allclose(E, np.cos(x), atol=1e-12)
+        np.testing.assert_allclose(dx, -g * np.sin(x), atol=1e-12)
+    # only RZ angles non-zero keeps the same expectations
+    gates = hea_gates(n, layers, ("RY", "RZ"))
+    theta = np.zeros(layers * 2 * n)
+    for l in range(layers):
+        theta[l * 2 * n + n: l * 2 * n + 2 * n] = np.linspace(0.3, 2.9, n)
+    x = np.random.default_rng(4).uniform(-math.pi, math.pi, size=(2, n))
+    xm, zm = z_observables(range(n))
+    np.testing.assert_allclose(orc.forward(n, gates, theta, x, xm, zm), np.cos(x), atol=1e-12)
+
+
+# ---------------------------------------------------------------- P4
+def pin_p4_norm(orc, n=9, layers=6):
+    gates = hea_gates(n, layers, ("RX", "RY", "RZ"))
+    rng = np.random.default_rng(5)
+    theta = rng.uniform(0, 2 * math.pi, size=layers * 3 * n)
+    x = rng.uniform(-math.pi, math.pi, size=(4, n))
+    xm, zm = z_observables([0])
+    E, psi = orc.forward(n, gates, theta, x, xm, zm, return_state=True)
+    np.testing.assert_allclose(np.sum(np.abs(psi) ** 2, axis=1), 1.0, atol=1e-12)
+    assert np.all(np.abs(E) <= 1.0 + 1e-12)
+
+
+# ---------------------------------------------------------------- P5
+def _u_dense(kind, phi):
+    P = {RX: PX, RY: PY, RZ: PZ}[kind]
+    return math.cos(phi / 2) * I2 - 1j * math.sin(phi / 2) * P
+
+
+def _embed(n, q, u):
+    """Kronecker embedding; qubit 0 is the rightmost factor."""
+    m = np.array([[1.0 + 0j]])
+    for k in reversed(range(n)):
+        m = np.kron(m, u if k == q else I2)
+    return m
+
+
+def _cz_dense(n, a, b):
+    d = np.ones(1 << n, dtype=np.complex128)
+    for i in range(1 << n):
+        if (i >> a) & 1 and (i >> b) & 1:
+            d[i] = -1
+    return np.diag(d)
+
+
+def dense_state(n, gates, theta, xb, psi0=None):
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1
+    if psi0 is not None:
+        psi = np.asarray(psi0, dtype=np.complex128).copy()
+    U = np.eye(1 << n, dtype=np.complex128)
+    for (k, q0, q1, t, f) in gates:
+        if k == CZ:
+            G = _cz_dense(n, q0, q1)
+        else:
+            phi = theta[t] if t >= 0 else xb[f]
+            G = _embed(n, q0, _u_dense(k, phi))
+        U = G @ U
+    return U @ psi
+
+
+def pin_p5_dense(orc):
+    rng = np.random.default_rng(6)
+    for n in (1, 2, 3, 5, 6):
+        rows = []
+        t = 0
+        for _ in range(4 * n + 3):
+            k = int(rng.integers(0, 4)) if n > 1 else int(rng.integers(0, 3))
+            q0 = int(rng.integers(0, n))
+            if k == CZ:
+                q1 = int((q0 + 1 + rng.integers(0, n - 1)) % n)
+                rows.append(_g(CZ, q0, q1))
+            elif rng.random() < 0.3:
+                rows.append(_g(k, q0, f=int(rng.integers(0, n))))
+            else:
+                rows.append(_g(k, q0, t=t))
+                t += 1
+        gates = _gates(rows)
+        theta = rng.uniform(0, 2 * math.pi, size=max(t, 1))
+        x = rng.uniform(-math.pi, math.pi, size=(2, n))
+        xm, zm = z_observables([0])
+        _, psi = orc.forward(n, gates, theta, x, xm, zm, return_state=True)
+        for b in range(2):
+            np.testing.assert_allclose(psi[b], dense_state(n, gates, theta, x[b]), atol=1e-12)
+
+
+# ---------------------------------------------------------------- P6
+def pin_p6_parameter_shift(orc, n=6, layers=4):
+    """dE/dphi = [E(phi + pi/2) - E(phi - pi/2)] / 2 for every gate angle."""
+    gates = hea_gates(n, layers, ("RX", "RY", "RZ"))
+    rng = np.random.default_rng(7)
+    P = layers * 3 * n
+    theta = rng.uniform(0, 2 * math.pi, size=P)
+    x = rng.uniform(-math.pi, math.pi, size=(1, n))
+    xm, zm = z_observables([0, 2, 5])
+    g = np.array([[0.7, -1.3, 0.4]])
+    _, dth, dx = orc.backward(n, gates, theta, x, xm, zm, g)
+
+    def L(th, xx):
+        return float((orc.forward(n, gates, th, xx, xm, zm) * g).sum())
+
+    for p in list(range(0, P, 7)) + [P - 1]:
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += math.pi / 2
+        tm[p] -= math.pi / 2
+        np.testing.assert_allclose(dth[p], 0.5 * (L(tp, x) - L(tm, x)), atol=1e-11)
+    for f in range(n):
+        xp, xmn = x.copy(), x.copy()
+        xp[0, f] += math.pi / 2
+        xmn[0, f] -= math.pi / 2
+        np.testing.assert_allclose(dx[0, f], 0.5 * (L(theta, xp) - L(theta, xmn)), atol=1e-11)
+
+
+# ---------------------------------------------------------------- P7
+def pin_p7_backward_modes(orc, n=5, layers=3):
+    """Un-apply backward == store-all backward == central finite differences;
+    a shared angle (used by two gates) receives the sum of both contributions."""
+    gates = hea_gates(n, layers, ("RY", "RZ"))
+    rows = [tuple(r) for r in gates.tolist()]
+    rows.append(_g(RX, 0, t=0))          # theta[0] drives two gates
+    rows.append(_g(RY, 3, f=1))          # x[:, 1] drives two gates
+    gates = _gates(rows)
+    rng = np.random.default_rng(8)
+    P = layers * 2 * n
+    theta = rng.uniform(0, 2 * math.pi, size=P)
+    x = rng.uniform(-math.pi, math.pi, size=(3, n))
+    xm, zm = z_observables([0, 3])
+    g = rng.normal(size=(3, 2))
+    E0, d0, x0 = orc.backward(n, gates, theta, x, xm, zm, g, mode=0)
+    E1, d1, x1 = orc.backward(n, gates, theta, x, xm, zm, g, mode=1)
+    np.testing.assert_allclose(d0, d1, atol=1e-12)
+    np.testing.assert_allclose(x0, x1, atol=1e-12)
+    np.testing.assert_allclose(E0, E1, atol=1e-13)
+
+    def L(th, xx):
+        return float((orc.forward(n, gates, th, xx, xm, zm) * g).sum())
+
+    h = 1e-5
+    for p in range(P):
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += h
+        tm[p] -= h
+        np.testing.assert_allclose(d0[p], (L(tp, x) - L(tm, x)) / (2 * h), atol=1e-8)
+    for b in range(3):
+        for f in range(n):
+            xp, xmn = x.copy(), x.copy()
+            xp[b, f] += h
+            xmn[b, f] -= h
+            np.testing.assert_allclose(x0[b, f], (L(theta, xp) - L(theta, xmn)) / (2 * h), atol=1e-8)
+
+
+# ---------------------------------------------------------------- P9
+def _pauli_dense(spec):
+    m = np.array([[1.0 + 0j]])
+    for ch in spec:          # leftmost character = highest qubit
+        m = np.kron(m, {"I": I2, "X": PX, "Y": PY, "Z": PZ}[ch])
+    return m
+
+
+def pin_p9_pauli_expectation(orc, n=5):
+    rng = np.random.default_rng(9)
+    gates = hea_gates(n, 2, ("RX", "RY", "RZ"))
+    theta = rng.uniform(0, 2 * math.pi, size=2 * 3 * n)
+    x = rng.uniform(-math.pi, math.pi, size=(2, n))
+    specs = ["IXYZI", "ZZZZZ", "YYIXX", "XIIIY", "IIIIZ", "YIIII"]
+    masks = [pauli_string(s) for s in specs]
+    xm = np.asarray([m[0] for m in masks], dtype=np.uint64)
+    zm = np.asarray([m[1] for m in masks], dtype=np.uint64)
+    E, psi = orc.forward(n, gates, theta, x, xm, zm, return_state=True)
+    for b in range(2):
+        for k, s in enumerate(specs):
+            ref = np.vdot(psi[b], _pauli_dense(s) @ psi[b]).real
+            np.testing.assert_allclose(E[b, k], ref, atol=1e-12)
+    # the adjoint seed with a general Pauli string agrees with finite differences
+    g = rng.normal(size=(2, len(specs)))
+    _, d0, _ = orc.backward(n, gates, theta, x, xm, zm, g)
+    h = 1e-5
+    for p in (0, 5, 17, 29):
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd = ((orc.forward(n, gates, tp, x, xm, zm) - orc.forward(n, gates, tm, x, xm, zm)) * g).sum() / (2 * h)
+        np.testing.assert_allclose(d0[p], fd, atol=1e-8)
+
+
+ALL_PINS = [pin_p1_single_qubit, pin_p2_two_qubit, pin_p3_zero_angles, pin_p4_norm,
+            pin_p5_dense, pin_p6_parameter_shift, pin_p7_backward_modes, pin_p9_pauli_expectation]
