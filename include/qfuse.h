@@ -1,0 +1,157 @@
+/*
+ * qfuse.h -- C-ABI of the fused forward / adjoint-gradient simulator for
+ * batched parameterised circuits (MI355X, gfx950).
+ *
+ * Method: "Fast and memory-efficient classical simulation of quantum machine
+ * learning via forward and backward gate fusion".  The library simulates a
+ * batch of state vectors, |psi_M(b)> = U_M ... U_1 |0...0>, returns the
+ * expectation values E[b][k] = <psi_M(b)| O_k |psi_M(b)> (Sec. 2.1) and, given
+ * upstream gradients dE[b][k] = dL/dE_k(b), the adjoint-method gradients with
+ * respect to every rotation angle (Sec. 2.2, eq. grad_theta, eq.
+ * update_adjoint_state, seeded by lambda_M = 2 sum_k g_k O_k psi_M, eq.
+ * bwd_exp_val plus the chain rule).  Runs of gates are fused so that each
+ * sample's state crosses HBM once per fused pass in the forward path (Sec. 3.2)
+ * and in the backward path, where intermediate states are recomputed in
+ * registers by un-applying gates (Sec. 3.3).  Only pass outputs inside the
+ * active checkpoint segment and one state per segment are stored (Sec. 3.4).
+ *
+ * Conventions
+ *  - Amplitude index x = sum_i x_i 2^i: qubit 0 is the least significant bit
+ *    (Sec. 3.1).
+ *  - Rotation u(phi) = cos(phi/2) I - i sin(phi/2) P, P in {X, Y, Z}
+ *    (Sec. 3.3, step 2).  CZ(c, t) negates amplitudes with bits c and t set.
+ *  - All device buffers are float32 and owned by the caller.  The library owns
+ *    only host objects (qf_circuit, qf_plan) and small device descriptor tables
+ *    that it allocates in qf_plan_create and frees in qf_plan_destroy.
+ *  - Calls are asynchronous on the given HIP stream (a hipStream_t passed as
+ *    void*, NULL = default stream).  Inputs are never modified.
+ *  - Errors are returned as status codes; nothing crosses the ABI as an
+ *    exception.  All validation is done on the host before any launch;
+ *    qf_last_error() gives a human-readable message for the calling thread.
+ *    Launch failures map to QF_ERR_DEVICE; asynchronous device faults surface
+ *    at the caller's next synchronisation.  NaN / Inf inputs propagate.
+ *  - Circuits and plans are immutable after creation except for the device
+ *    tables a plan owns; one stream per concurrent call on the same plan.
+ */
+#ifndef QFUSE_H
+#define QFUSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QF_OK = 0,
+  QF_ERR_INVALID_ARG = 1,  /* bad pointer, index out of range, inconsistent sizes   */
+  QF_ERR_UNSUPPORTED = 2,  /* valid request this build does not implement          */
+  QF_ERR_WORKSPACE = 3,    /* workspace missing or smaller than qf_workspace_size  */
+  QF_ERR_OOM = 4,          /* host or device allocation of plan tables failed      */
+  QF_ERR_DEVICE = 5,       /* a HIP call or kernel launch failed                   */
+  QF_ERR_INTERNAL = 6
+} qf_status;
+
+/* Gate kinds (Sec. 3.1): Pauli rotations and CZ. */
+typedef enum { QF_RX = 0, QF_RY = 1, QF_RZ = 2, QF_CZ = 3 } qf_gate_kind;
+
+/*
+ * One gate.  Layout-compatible with int32[5].
+ *  - rotations: q0 = target qubit, q1 = -1; the angle is theta[theta_idx] when
+ *    theta_idx >= 0, else x[b][input_idx] (an input-encoding angle, per sample);
+ *    exactly one of the two indices is >= 0.
+ *  - CZ: q0 != q1, both in [0, n_qubits); theta_idx = input_idx = -1.
+ * An angle index used by several gates receives the sum of their gradients.
+ */
+typedef struct { int32_t kind, q0, q1, theta_idx, input_idx; } qf_gate;
+
+/* Pauli-string observable: X on x_mask bits, Z on z_mask bits (Y on both).
+   The hot path supports Z strings only (x_mask == 0); others: QF_ERR_UNSUPPORTED. */
+typedef struct { uint64_t x_mask, z_mask; } qf_pauli;
+
+typedef struct {
+  int32_t n_qubits;         /* 1..30 (state of 2^n complex64 per sample)         */
+  int32_t n_params;         /* length of theta                                    */
+  int32_t n_inputs;         /* features per sample (row length of x)              */
+  const qf_gate* gates;     /* n_gates gates in application order                 */
+  int64_t n_gates;
+  const qf_pauli* obs;      /* n_obs observables; E has n_obs columns             */
+  int32_t n_obs;
+} qf_circuit_desc;
+
+/* Execution choices.  0 (or -1 for store_ckpt) selects the built-in default. */
+typedef struct {
+  int32_t mode;             /* 0 = fused passes, 1 = one kernel per gate (baseline)   */
+  int32_t tile_qubits;      /* k: amplitudes per workgroup tile = 2^k, k <= 13         */
+  int32_t reg_qubits;       /* r: register-resident qubits per lane (1..5)             */
+  int32_t fusion_depth;     /* max rotation runs applied to one qubit in one pass      */
+  int32_t ckpt_interval;    /* fused passes per checkpoint segment                     */
+  int32_t micro_batch;      /* samples per backward micro-batch                        */
+  int32_t store_ckpt;       /* 1 = forward keeps segment checkpoints for the batch,
+                               0 = backward re-runs the forward per micro-batch        */
+} qf_tuning;
+
+/* Static description of a plan, for accounting and roofline reporting. */
+typedef struct {
+  int32_t n_qubits, tile_qubits, reg_qubits, threads, tiles;
+  int32_t fused_passes;       /* forward passes for one sample                       */
+  int32_t segments;           /* checkpoint segments                                 */
+  int32_t ckpt_interval, micro_batch, store_ckpt, fusion_depth;
+  int64_t n_runs;             /* fused single-qubit runs                              */
+  int64_t n_perm, n_u2, n_cz; /* ops per sample summed over forward passes            */
+  double fwd_bytes_per_sample;   /* algorithmic HBM bytes, forward                    */
+  double bwd_bytes_per_sample;   /* algorithmic HBM bytes, backward incl. recompute   */
+  double fwd_flops_per_sample;   /* algorithmic fp32 flops, forward                   */
+  double bwd_flops_per_sample;   /* algorithmic fp32 flops, backward incl. recompute  */
+  double bwd_pass_bytes_per_sample;  /* bytes of the fused adjoint pass kernel only   */
+  double bwd_pass_flops_per_sample;  /* flops of the fused adjoint pass kernel only   */
+  int64_t bwd_pass_launches;         /* adjoint pass launches per backward call       */
+} qf_plan_info;
+
+typedef struct qf_circuit qf_circuit;
+typedef struct qf_plan qf_plan;
+
+/* Validates and copies the description (host only).  Ownership of *out passes
+   to the caller; release with qf_circuit_destroy. */
+qf_status qf_circuit_create(const qf_circuit_desc* desc, qf_circuit** out);
+qf_status qf_circuit_destroy(qf_circuit* circuit);
+
+/* Builds the pass schedule for `batch` samples and uploads its descriptor
+   tables to the current HIP device.  tuning may be NULL (defaults). */
+qf_status qf_plan_create(const qf_circuit* circuit, int32_t batch, const qf_tuning* tuning,
+                         qf_plan** out);
+qf_status qf_plan_destroy(qf_plan* plan);
+qf_status qf_plan_get_info(const qf_plan* plan, qf_plan_info* info);
+
+/* Device workspace (bytes, 256-byte aligned start expected) that qf_forward and
+   qf_backward need: checkpoints, stored pass outputs, adjoint states, partial
+   sums and coefficient tables. */
+qf_status qf_workspace_size(const qf_plan* plan, size_t* bytes);
+
+/*
+ * Forward pass.  theta: device float[n_params]; x: device float[batch][n_inputs]
+ * (may be NULL when n_inputs == 0); E: device float[batch][n_obs], overwritten.
+ * ws must stay untouched until the matching qf_backward has been enqueued.
+ */
+qf_status qf_forward(qf_plan* plan, const float* theta, const float* x, float* E,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Backward pass: dE device float[batch][n_obs] = dL/dE.  Writes
+ *   dtheta: device float[n_params] = sum over the batch (overwritten),
+ *   dx:     device float[batch][n_inputs] (overwritten; may be NULL).
+ * Needs the same ws, theta and x as the preceding qf_forward on this plan.
+ */
+qf_status qf_backward(qf_plan* plan, const float* theta, const float* x, const float* dE,
+                      float* dtheta, float* dx, void* ws, size_t ws_bytes, void* stream);
+
+const char* qf_status_string(qf_status status);
+/* Detail of the last error on the calling thread ("" if none). */
+const char* qf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QFUSE_H */

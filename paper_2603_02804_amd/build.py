@@ -1,0 +1,56 @@
+"""Builds the in-tree native libraries.
+
+  libqfuse.so            HIP kernels + host planner + C-ABI (hipcc, gfx950)
+  libqfuse_plancheck.so  test-only CPU execution of the planner's programs (g++)
+
+Every HIP source is compiled for gfx950 with packed FP32 instructions disabled.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(PKG, "libqfuse.so")
+PLANCHECK = os.path.join(PKG, "libqfuse_plancheck.so")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             "-Wno-unused-result", "-Wno-unused-value"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError(f"build failed: {' '.join(cmd)}")
+
+
+def build_hip(out: str = LIB) -> str:
+    srcs = [os.path.join(CSRC, "plan.cpp"), os.path.join(CSRC, "qfuse.hip")]
+    tmp = out + ".tmp"
+    _run([HIPCC, *HIP_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-o", tmp])
+    os.replace(tmp, out)
+    return out
+
+
+def build_plancheck(out: str = PLANCHECK) -> str:
+    srcs = [os.path.join(CSRC, "plan.cpp"), os.path.join(CSRC, "plancheck.cpp")]
+    tmp = out + ".tmp"
+    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-o", tmp])
+    os.replace(tmp, out)
+    return out
+
+
+def build_all() -> None:
+    build_hip()
+    build_plancheck()
+
+
+if __name__ == "__main__":
+    build_all()

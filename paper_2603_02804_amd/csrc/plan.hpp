@@ -1,0 +1,71 @@
+// plan.hpp -- host planner: gate list -> fused pass schedule.
+//
+// Forward fusion (Sec. 3.2): consecutive single-qubit rotations on one qubit are
+// merged into one 2x2 "run"; a pass applies every run and CZ that is ready and
+// whose qubit is local to the pass's tile, reading and writing the state once.
+// Backward fusion (Sec. 3.3): each pass has a mirrored program that starts from
+// the stored pass output and the adjoint state, and for every run, in reverse
+// order, evaluates the functionals that give the run's gradients and un-applies
+// the run from both states in registers.  CZ gates are real and self-adjoint, so
+// the same sign operation serves both directions (App. B.1).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "plan_types.hpp"
+#include "qfuse.h"
+
+namespace qf {
+
+struct Circuit {
+  int n = 0, P = 0, F = 0, K = 0;
+  std::vector<qf_gate> gates;
+  std::vector<qf_pauli> obs;
+};
+
+// Returns QF_OK or a status with a message; checks every index and size.
+qf_status validate_circuit(const qf_circuit_desc* d, std::string* msg);
+
+struct Tuning {
+  int mode = 0;          // 0 fused, 1 per-gate
+  int k = 0;             // tile qubits
+  int R = 0;             // register qubits
+  int fusion = 0;        // runs per qubit per pass
+  int ckpt = 0;          // passes per checkpoint segment
+  int micro = 0;         // samples per micro-batch
+  int store = -1;        // keep checkpoints of the whole batch in the forward
+};
+
+struct Schedule {
+  int n = 0, k = 0, R = 0, NT = 0, active = 0, tiles_log2 = 0, thread_bits = 0;
+  int fusion = 0;
+  std::vector<RunRec> runs;
+  std::vector<int32_t> run_gates;     // GateRec indices of each run, forward order
+  std::vector<GateRec> gates;         // rotations in circuit order
+  int n_coef_shared = 0, n_coef_ps = 0;
+  std::vector<PassRec> passes;
+  std::vector<Op> ops;
+  std::vector<LayoutRec> layouts;
+  std::vector<CzGroup> czg;
+  std::vector<FuncEntry> funcs;
+  // per-sample op counts over all forward passes
+  int64_t n_perm = 0, n_u2 = 0, n_cz = 0;
+};
+
+// Fused schedule.  Fails only on internal inconsistencies (the circuit is
+// validated before).
+bool build_schedule(const Circuit& c, const Tuning& t, Schedule* s, std::string* msg);
+
+// Runs and gate tables only, one run per rotation gate (the per-gate baseline).
+void build_gate_runs(const Circuit& c, Schedule* s);
+
+// Swizzled LDS element index of tile index i.
+inline uint32_t lds_swizzle(uint32_t i) {
+  uint32_t f = 0;
+  for (uint32_t h = i >> kSwizzleBits; h; h >>= kSwizzleBits) f ^= h;
+  return i ^ (f & ((1u << kSwizzleBits) - 1));
+}
+
+}  // namespace qf

@@ -1,0 +1,564 @@
+// plancheck.cpp -- CPU execution of fused pass programs, for testing the planner.
+//
+// TEST-ONLY.  Built into libqfuse_plancheck.so, which the product library never
+// links or loads.  It runs the planner's op programs with the same per-lane
+// register / LDS / address-table semantics as the pass kernels, one emulated
+// thread at a time, so that schedules, layouts, memory maps and the driver's
+// segment and micro-batch sequencing can be checked against the oracle without a
+// GPU.  It is not a fallback: the device entry points never reach this code.
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "driver.hpp"
+
+namespace qf {
+namespace {
+
+using cd = std::complex<double>;
+
+struct M2 {
+  cd m[4];
+};
+
+M2 mul(const M2& a, const M2& b) {
+  M2 r;
+  r.m[0] = a.m[0] * b.m[0] + a.m[1] * b.m[2];
+  r.m[1] = a.m[0] * b.m[1] + a.m[1] * b.m[3];
+  r.m[2] = a.m[2] * b.m[0] + a.m[3] * b.m[2];
+  r.m[3] = a.m[2] * b.m[1] + a.m[3] * b.m[3];
+  return r;
+}
+
+M2 rot(int kind, double phi) {
+  const double c = std::cos(0.5 * phi), s = std::sin(0.5 * phi);
+  M2 u;
+  if (kind == QF_RX) { u.m[0] = c; u.m[1] = cd(0, -s); u.m[2] = cd(0, -s); u.m[3] = c; }
+  else if (kind == QF_RY) { u.m[0] = c; u.m[1] = -s; u.m[2] = s; u.m[3] = c; }
+  else { u.m[0] = cd(c, -s); u.m[1] = 0; u.m[2] = 0; u.m[3] = cd(c, s); }
+  return u;
+}
+
+M2 pauli(int kind) {
+  M2 p;
+  if (kind == QF_RX) { p.m[0] = 0; p.m[1] = 1; p.m[2] = 1; p.m[3] = 0; }
+  else if (kind == QF_RY) { p.m[0] = 0; p.m[1] = cd(0, -1); p.m[2] = cd(0, 1); p.m[3] = 0; }
+  else { p.m[0] = 1; p.m[1] = 0; p.m[2] = 0; p.m[3] = -1; }
+  return p;
+}
+
+M2 dag(const M2& a) {
+  M2 r;
+  r.m[0] = std::conj(a.m[0]);
+  r.m[1] = std::conj(a.m[2]);
+  r.m[2] = std::conj(a.m[1]);
+  r.m[3] = std::conj(a.m[3]);
+  return r;
+}
+
+struct CF {
+  float re, im;
+};
+
+inline CF cmul(float ar, float ai, CF b) { return {ar * b.re - ai * b.im, ar * b.im + ai * b.re}; }
+
+[[noreturn]] void oob(const char* what) { throw std::runtime_error(std::string("out of bounds: ") + what); }
+
+struct CpuExec {
+  const PlanCore& c;
+  const char* ws_lo = nullptr;   // workspace range every state / partial access must stay in
+  const char* ws_hi = nullptr;
+  void in_ws(const void* p, size_t bytes, const char* what) const {
+    const char* q = (const char*)p;
+    if (ws_lo && (q < ws_lo || q + bytes > ws_hi)) oob(what);
+  }
+  const float* theta = nullptr;
+  const float* x = nullptr;
+  const float* coef_sh = nullptr;
+  const float* coef_ps = nullptr;
+  explicit CpuExec(const PlanCore& pc) : c(pc) {}
+
+  qf_status status() const { return QF_OK; }
+
+  double angle(const GateRec& g, int sample) const {
+    return g.theta_idx >= 0 ? (double)theta[g.theta_idx] : (double)x[(int64_t)sample * c.C.F + g.input_idx];
+  }
+  M2 run_matrix(int r, int sample) const {
+    const RunRec& rr = c.S.runs[r];
+    M2 U;
+    U.m[0] = 1; U.m[1] = 0; U.m[2] = 0; U.m[3] = 1;
+    for (int i = 0; i < rr.gate_count; ++i) {
+      const GateRec& g = c.S.gates[c.S.run_gates[rr.gate_begin + i]];
+      U = mul(rot(g.kind, angle(g, sample)), U);
+    }
+    return U;
+  }
+  static void put(float* dst, const M2& U) {
+    for (int i = 0; i < 4; ++i) {
+      dst[2 * i] = (float)U.m[i].real();
+      dst[2 * i + 1] = (float)U.m[i].imag();
+    }
+  }
+
+  void coef(const float* th, const float* xx, float* csh, float* cps) {
+    theta = th;
+    x = xx;
+    coef_sh = csh;
+    coef_ps = cps;
+    for (size_t i = 0; i < c.coef_runs_sh.size(); ++i) put(csh + 8 * i, run_matrix(c.coef_runs_sh[i], 0));
+    const int nps = (int)c.coef_runs_ps.size();
+    for (int b = 0; b < c.B; ++b)
+      for (int i = 0; i < nps; ++i) put(cps + 8 * ((int64_t)b * nps + i), run_matrix(c.coef_runs_ps[i], b));
+  }
+
+  const float* coef_row(int ref, int sample) const {
+    if (ref >= 0) return coef_sh + 8 * ref;
+    return coef_ps + 8 * ((int64_t)sample * c.S.n_coef_ps + (-1 - ref));
+  }
+
+  // ---------------------------------------------------------------- fused pass
+  void pass(const PassLaunch& L) {
+    const Schedule& S = c.S;
+    const PassRec& pr = S.passes[L.pass];
+    const int R = S.R, NA = 1 << R, tb = S.thread_bits, active = S.active;
+    const int tiles = c.tiles, waves = c.waves, K = c.C.K;
+    const int b0 = L.bwd ? pr.bop_begin : pr.fop_begin;
+    const int nops = L.bwd ? pr.bop_count : pr.fop_count;
+    const int64_t k_amps = int64_t(1) << S.k;
+    std::vector<CF> a(size_t(active) * NA), l(size_t(active) * NA), lds(k_amps);
+    for (int sl = 0; sl < L.nb; ++sl) {
+      const int sample = L.sample0 + sl;
+      for (int tile = 0; tile < tiles; ++tile) {
+        uint32_t tlog = 0, tin = 0, tout = 0;
+        for (int i = 0; i < pr.n_nonlocal; ++i)
+          if ((tile >> i) & 1) {
+            tlog |= 1u << pr.nl_log[i];
+            tin |= 1u << pr.nl_in[i];
+            tout |= 1u << pr.nl_out[i];
+          }
+        std::fill(a.begin(), a.end(), CF{0, 0});
+        std::fill(l.begin(), l.end(), CF{0, 0});
+        auto tbase = [&](const uint32_t* tab, int t) {
+          uint32_t v = 0;
+          for (int i = 0; i < tb; ++i)
+            if ((t >> i) & 1) v ^= tab[i];
+          return v;
+        };
+        const int64_t item = (int64_t)sl * tiles + tile;
+        for (int oi = 0; oi < nops; ++oi) {
+          const Op& op = S.ops[b0 + oi];
+          switch (op.kind) {
+            case OP_INIT0: {
+              const LayoutRec& Ly = S.layouts[op.a];
+              for (int t = 0; t < active; ++t)
+                for (int jj = 0; jj < NA; ++jj) {
+                  uint32_t xl = tlog | tbase(Ly.log_thr, t) | Ly.log_reg[jj];
+                  a[t * NA + jj] = (xl == 0) ? CF{1, 0} : CF{0, 0};
+                }
+              break;
+            }
+            case OP_LOAD: {
+              const LayoutRec& Ly = S.layouts[op.a];
+              const float* src = op.b == 0 ? L.src0 : L.src1;
+              const int64_t stride = op.b == 0 ? L.src0_stride : L.src1_stride;
+              std::vector<CF>& v = op.b == 0 ? a : l;
+              const uint32_t tm = op.c ? tout : tin;
+              for (int t = 0; t < active; ++t)
+                for (int jj = 0; jj < NA; ++jj) {
+                  uint64_t idx = tm | tbase(Ly.mem_thr, t) | Ly.mem_reg[jj];
+                  if (idx >= (uint64_t)c.amps) oob("load index");
+                  const float* p = src + sl * stride + 2 * idx;
+                  in_ws(p, 8, "load address");
+                  v[t * NA + jj] = CF{p[0], p[1]};
+                }
+              break;
+            }
+            case OP_STORE: {
+              const LayoutRec& Ly = S.layouts[op.a];
+              const std::vector<CF>& v = L.bwd ? l : a;
+              const uint32_t tm = op.c ? tout : tin;
+              if (!L.dst) break;
+              for (int t = 0; t < active; ++t)
+                for (int jj = 0; jj < NA; ++jj) {
+                  uint64_t idx = tm | tbase(Ly.mem_thr, t) | Ly.mem_reg[jj];
+                  if (idx >= (uint64_t)c.amps) oob("store index");
+                  float* p = L.dst + sl * L.dst_stride + 2 * idx;
+                  in_ws(p, 8, "store address");
+                  p[0] = v[t * NA + jj].re;
+                  p[1] = v[t * NA + jj].im;
+                }
+              break;
+            }
+            case OP_PERM: {
+              const LayoutRec& F = S.layouts[op.a];
+              const LayoutRec& T = S.layouts[op.b];
+              for (int which = 0; which < (L.bwd ? 2 : 1); ++which) {
+                std::vector<CF>& v = which == 0 ? a : l;
+                std::vector<char> seen(k_amps, 0);
+                for (int t = 0; t < active; ++t)
+                  for (int jj = 0; jj < NA; ++jj) {
+                    uint32_t e = tbase(F.lds_thr, t) ^ F.lds_reg[jj];
+                    if (e >= k_amps || seen[e]) throw std::runtime_error("LDS layout is not a bijection");
+                    seen[e] = 1;
+                    lds[e] = v[t * NA + jj];
+                  }
+                for (int t = 0; t < active; ++t)
+                  for (int jj = 0; jj < NA; ++jj) {
+                    uint32_t e = tbase(T.lds_thr, t) ^ T.lds_reg[jj];
+                    if (e >= k_amps) oob("LDS read");
+                    v[t * NA + jj] = lds[e];
+                  }
+              }
+              break;
+            }
+            case OP_U2:
+            case OP_U2ADJ: {
+              const float* u = coef_row(op.b, sample);
+              float u00r = u[0], u00i = u[1], u01r = u[2], u01i = u[3], u10r = u[4], u10i = u[5], u11r = u[6],
+                    u11i = u[7];
+              if (op.kind == OP_U2ADJ) {
+                float t01r = u01r, t01i = u01i;
+                u00i = -u00i;
+                u11i = -u11i;
+                u01r = u10r; u01i = -u10i;
+                u10r = t01r; u10i = -t01i;
+              }
+              const int j = op.a;
+              for (int which = 0; which < (op.kind == OP_U2ADJ ? 2 : 1); ++which) {
+                std::vector<CF>& v = which == 0 ? a : l;
+                for (int t = 0; t < active; ++t)
+                  for (int jj = 0; jj < NA; ++jj) {
+                    if ((jj >> j) & 1) continue;
+                    CF x0 = v[t * NA + jj], x1 = v[t * NA + (jj | (1 << j))];
+                    CF p = cmul(u00r, u00i, x0), q = cmul(u01r, u01i, x1);
+                    CF r0{p.re + q.re, p.im + q.im};
+                    p = cmul(u10r, u10i, x0);
+                    q = cmul(u11r, u11i, x1);
+                    CF r1{p.re + q.re, p.im + q.im};
+                    v[t * NA + jj] = r0;
+                    v[t * NA + (jj | (1 << j))] = r1;
+                  }
+              }
+              break;
+            }
+            case OP_CZ: {
+              const LayoutRec& Ly = S.layouts[op.a];
+              for (int t = 0; t < active; ++t)
+                for (int jj = 0; jj < NA; ++jj) {
+                  uint32_t xl = tlog | tbase(Ly.log_thr, t) | Ly.log_reg[jj];
+                  uint32_t par = 0;
+                  for (int gi = 0; gi < op.c; ++gi) {
+                    const CzGroup& g = S.czg[op.b + gi];
+                    par ^= xl & (xl >> g.shift) & g.mask;
+                  }
+                  if (__builtin_popcount(par) & 1) {
+                    CF& v = a[t * NA + jj];
+                    v = CF{-v.re, -v.im};
+                    if (L.bwd) {
+                      CF& w = l[t * NA + jj];
+                      w = CF{-w.re, -w.im};
+                    }
+                  }
+                }
+              break;
+            }
+            case OP_EXPECT: {
+              if (!L.do_expect) break;
+              const LayoutRec& Ly = S.layouts[op.a];
+              for (int w = 0; w < waves; ++w)
+                for (int k = 0; k < K; ++k) {
+                  float acc = 0;
+                  for (int t = w * 64; t < std::min(active, (w + 1) * 64); ++t)
+                    for (int jj = 0; jj < NA; ++jj) {
+                      uint32_t xl = tlog | tbase(Ly.log_thr, t) | Ly.log_reg[jj];
+                      CF v = a[t * NA + jj];
+                      float p = v.re * v.re + v.im * v.im;
+                      acc += (__builtin_popcount(xl & (uint32_t)c.C.obs[k].z_mask) & 1) ? -p : p;
+                    }
+                  const int64_t pe = (item * waves + w) * K + k;
+                  if (pe >= (int64_t)L.nb * tiles * waves * K) oob("partE");
+                  in_ws(L.partE + pe, 4, "partE address");
+                  L.partE[pe] = acc;
+                }
+              break;
+            }
+            case OP_SEED: {
+              const LayoutRec& Ly = S.layouts[op.a];
+              for (int t = 0; t < active; ++t)
+                for (int jj = 0; jj < NA; ++jj) {
+                  uint32_t xl = tlog | tbase(Ly.log_thr, t) | Ly.log_reg[jj];
+                  float cc = 0;
+                  for (int k = 0; k < K; ++k) {
+                    float g = L.dE[(int64_t)sample * K + k];
+                    cc += (__builtin_popcount(xl & (uint32_t)c.C.obs[k].z_mask) & 1) ? -g : g;
+                  }
+                  CF v = a[t * NA + jj];
+                  l[t * NA + jj] = CF{2 * cc * v.re, 2 * cc * v.im};
+                }
+              break;
+            }
+            case OP_FUNC: {
+              const int ns = pr.n_slots;
+              for (int e = 0; e < op.a; ++e) {
+                const FuncEntry& fe = S.funcs[op.b + e];
+                const int j = fe.regbit;
+                for (int w = 0; w < waves; ++w) {
+                  float fx = 0, fy = 0, fz = 0;
+                  for (int t = w * 64; t < std::min(active, (w + 1) * 64); ++t)
+                    for (int jj = 0; jj < NA; ++jj) {
+                      if ((jj >> j) & 1) continue;
+                      CF p0 = a[t * NA + jj], p1 = a[t * NA + (jj | (1 << j))];
+                      CF l0 = l[t * NA + jj], l1 = l[t * NA + (jj | (1 << j))];
+                      fx += l0.re * p1.im - l0.im * p1.re + l1.re * p0.im - l1.im * p0.re;
+                      fy += -(l0.re * p1.re + l0.im * p1.im) + (l1.re * p0.re + l1.im * p0.im);
+                      fz += (l0.re * p0.im - l0.im * p0.re) - (l1.re * p1.im - l1.im * p1.re);
+                    }
+                  const int64_t pf = (item * waves + w) * 3 * ns + 3 * fe.slot;
+                  if (fe.slot < 0 || fe.slot >= ns || pf + 3 > (int64_t)L.nb * tiles * waves * 3 * ns) oob("partF");
+                  float* dst = L.partF + pf;
+                  in_ws(dst, 12, "partF address");
+                  dst[0] = fx;
+                  dst[1] = fy;
+                  dst[2] = fz;
+                }
+              }
+              break;
+            }
+            default:
+              throw std::runtime_error("unknown op");
+          }
+        }
+      }
+    }
+  }
+
+  void reduce_E(int nb, int sample0, const float* partE, float* E) {
+    const int K = c.C.K;
+    for (int s = 0; s < nb; ++s)
+      for (int k = 0; k < K; ++k) {
+        double acc = 0;
+        for (int i = 0; i < c.tiles * c.waves; ++i) acc += partE[((int64_t)s * c.tiles * c.waves + i) * K + k];
+        E[(int64_t)(sample0 + s) * K + k] = (float)acc;
+      }
+  }
+
+  // grad_i = 1/2 Im<lambda| K_i P_i K_i^dag |psi> at the cut after the run,
+  // K_i = product of the run's gates after gate i.
+  void run_grads(int r, int sample, double fx, double fy, double fz, float* Grow) const {
+    const RunRec& rr = c.S.runs[r];
+    M2 Kc;
+    Kc.m[0] = 1; Kc.m[1] = 0; Kc.m[2] = 0; Kc.m[3] = 1;
+    for (int i = rr.gate_count - 1; i >= 0; --i) {
+      const GateRec& g = c.S.gates[c.S.run_gates[rr.gate_begin + i]];
+      M2 G = mul(mul(Kc, pauli(g.kind)), dag(Kc));
+      double gr = 0.5 * (G.m[2].real() * fx + G.m[2].imag() * fy + G.m[0].real() * fz);
+      Grow[g.out_idx] = (float)gr;
+      Kc = mul(Kc, rot(g.kind, angle(g, sample)));
+    }
+  }
+
+  void assemble(int seg, int nb, int sample0, const float*, const float*, const float* partF, float* Gr) {
+    for (int s = 0; s < nb; ++s)
+      for (int i = c.seg_run_begin[seg]; i < c.seg_run_begin[seg + 1]; ++i) {
+        const int r = c.seg_runs[i];
+        const RunRec& rr = c.S.runs[r];
+        const int ns = c.S.passes[rr.pass].n_slots;
+        const float* base = partF + (int64_t)nb * c.partF_off[rr.pass];
+        double f[3] = {0, 0, 0};
+        for (int it = 0; it < c.tiles * c.waves; ++it)
+          for (int P = 0; P < 3; ++P) f[P] += base[(((int64_t)s * c.tiles * c.waves) + it) * 3 * ns + 3 * rr.slot + P];
+        run_grads(r, sample0 + s, f[0], f[1], f[2], Gr + (int64_t)s * c.n_angle);
+      }
+  }
+
+  void reduce_grads(int nb, int sample0, const float* Gr, float* dtheta, float* dx, bool accumulate) {
+    for (int p = 0; p < c.C.P; ++p) {
+      double acc = 0;
+      for (int s = 0; s < nb; ++s)
+        for (int i = c.th_ref_begin[p]; i < c.th_ref_begin[p + 1]; ++i) acc += Gr[(int64_t)s * c.n_angle + c.th_refs[i]];
+      dtheta[p] = accumulate ? dtheta[p] + (float)acc : (float)acc;
+    }
+    if (dx)
+      for (int s = 0; s < nb; ++s)
+        for (int f = 0; f < c.C.F; ++f) {
+          double acc = 0;
+          for (int i = c.in_ref_begin[f]; i < c.in_ref_begin[f + 1]; ++i) acc += Gr[(int64_t)s * c.n_angle + c.in_refs[i]];
+          dx[(int64_t)(sample0 + s) * c.C.F + f] = (float)acc;
+        }
+  }
+
+  // ---------------------------------------------------------------- per-gate baseline
+  void pg_init(float* psi, int nb) {
+    for (int s = 0; s < nb; ++s) {
+      std::memset(psi + s * 2 * c.amps, 0, sizeof(float) * 2 * c.amps);
+      psi[s * 2 * c.amps] = 1;
+    }
+  }
+  void pg_copy(float* dst, const float* src, int nb) { std::memcpy(dst, src, sizeof(float) * 2 * c.amps * nb); }
+  void apply1(float* v, int q, const float* u) {
+    const int64_t st = int64_t(1) << q;
+    for (int64_t i = 0; i < c.amps; ++i) {
+      if (i & st) continue;
+      CF x0{v[2 * i], v[2 * i + 1]}, x1{v[2 * (i | st)], v[2 * (i | st) + 1]};
+      CF p = cmul(u[0], u[1], x0), q2 = cmul(u[2], u[3], x1);
+      CF r = cmul(u[4], u[5], x0), s2 = cmul(u[6], u[7], x1);
+      v[2 * i] = p.re + q2.re; v[2 * i + 1] = p.im + q2.im;
+      v[2 * (i | st)] = r.re + s2.re; v[2 * (i | st) + 1] = r.im + s2.im;
+    }
+  }
+  void pg_rot(float* psi, int nb, int sample0, int r, const float*, const float*) {
+    for (int s = 0; s < nb; ++s) apply1(psi + s * 2 * c.amps, c.S.runs[r].q, coef_row(c.S.runs[r].coef, sample0 + s));
+  }
+  void pg_cz(float* psi, float* lam, int nb, int qa, int qb) {
+    for (int s = 0; s < nb; ++s)
+      for (int64_t i = 0; i < c.amps; ++i)
+        if (((i >> qa) & 1) && ((i >> qb) & 1)) {
+          for (int w = 0; w < 2; ++w) {
+            float* v = (w == 0 ? psi : lam);
+            if (!v) continue;
+            v[s * 2 * c.amps + 2 * i] *= -1;
+            v[s * 2 * c.amps + 2 * i + 1] *= -1;
+          }
+        }
+  }
+  void pg_expect(const float* psi, int nb, float* partE) {
+    for (int s = 0; s < nb; ++s)
+      for (int k = 0; k < c.C.K; ++k) {
+        double acc = 0;
+        for (int64_t i = 0; i < c.amps; ++i) {
+          double p = (double)psi[s * 2 * c.amps + 2 * i] * psi[s * 2 * c.amps + 2 * i] +
+                     (double)psi[s * 2 * c.amps + 2 * i + 1] * psi[s * 2 * c.amps + 2 * i + 1];
+          acc += (__builtin_popcountll((uint64_t)i & c.C.obs[k].z_mask) & 1) ? -p : p;
+        }
+        for (int b = 0; b < c.pg_blocks; ++b) partE[((int64_t)s * c.pg_blocks + b) * c.C.K + k] = b == 0 ? (float)acc : 0.f;
+      }
+  }
+  void pg_reduce_E(int nb, int sample0, const float* partE, float* E) {
+    for (int s = 0; s < nb; ++s)
+      for (int k = 0; k < c.C.K; ++k) {
+        double acc = 0;
+        for (int b = 0; b < c.pg_blocks; ++b) acc += partE[((int64_t)s * c.pg_blocks + b) * c.C.K + k];
+        E[(int64_t)(sample0 + s) * c.C.K + k] = (float)acc;
+      }
+  }
+  void pg_seed(const float* psi, float* lam, int nb, int sample0, const float* dE) {
+    for (int s = 0; s < nb; ++s)
+      for (int64_t i = 0; i < c.amps; ++i) {
+        double cc = 0;
+        for (int k = 0; k < c.C.K; ++k)
+          cc += ((__builtin_popcountll((uint64_t)i & c.C.obs[k].z_mask) & 1) ? -1.0 : 1.0) * dE[(int64_t)(sample0 + s) * c.C.K + k];
+        lam[s * 2 * c.amps + 2 * i] = (float)(2 * cc * psi[s * 2 * c.amps + 2 * i]);
+        lam[s * 2 * c.amps + 2 * i + 1] = (float)(2 * cc * psi[s * 2 * c.amps + 2 * i + 1]);
+      }
+  }
+  void pg_rot_bwd(float* psi, float* lam, int nb, int sample0, int r, int slot, const float*, const float*, float* partF) {
+    const int q = c.S.runs[r].q;
+    const int64_t st = int64_t(1) << q;
+    for (int s = 0; s < nb; ++s) {
+      float* P = psi + s * 2 * c.amps;
+      float* Lm = lam + s * 2 * c.amps;
+      double fx = 0, fy = 0, fz = 0;
+      for (int64_t i = 0; i < c.amps; ++i) {
+        if (i & st) continue;
+        const int64_t j = i | st;
+        double p0r = P[2 * i], p0i = P[2 * i + 1], p1r = P[2 * j], p1i = P[2 * j + 1];
+        double l0r = Lm[2 * i], l0i = Lm[2 * i + 1], l1r = Lm[2 * j], l1i = Lm[2 * j + 1];
+        fx += l0r * p1i - l0i * p1r + l1r * p0i - l1i * p0r;
+        fy += -(l0r * p1r + l0i * p1i) + (l1r * p0r + l1i * p0i);
+        fz += (l0r * p0i - l0i * p0r) - (l1r * p1i - l1i * p1r);
+      }
+      float* dst = partF + (((int64_t)s * c.pg_chunk + slot) * c.pg_blocks) * 3;
+      for (int b = 0; b < c.pg_blocks; ++b) {
+        dst[3 * b] = b == 0 ? (float)fx : 0.f;
+        dst[3 * b + 1] = b == 0 ? (float)fy : 0.f;
+        dst[3 * b + 2] = b == 0 ? (float)fz : 0.f;
+      }
+      const float* u = coef_row(c.S.runs[r].coef, sample0 + s);
+      float ud[8] = {u[0], -u[1], u[4], -u[5], u[2], -u[3], u[6], -u[7]};
+      apply1(P, q, ud);
+      apply1(Lm, q, ud);
+    }
+  }
+  void pg_assemble(int r0, int cnt, int nb, int sample0, const float* partF, float* Gr) {
+    for (int s = 0; s < nb; ++s)
+      for (int i = 0; i < cnt; ++i) {
+        const int r = r0 + i, slot = r % c.pg_chunk;
+        double f[3] = {0, 0, 0};
+        for (int b = 0; b < c.pg_blocks; ++b)
+          for (int P = 0; P < 3; ++P) f[P] += partF[(((int64_t)s * c.pg_chunk + slot) * c.pg_blocks + b) * 3 + P];
+        run_grads(r, sample0 + s, f[0], f[1], f[2], Gr + (int64_t)s * c.n_angle);
+      }
+  }
+};
+
+thread_local std::string g_err;
+
+}  // namespace
+}  // namespace qf
+
+using namespace qf;
+
+extern "C" {
+
+// Runs forward and backward for a circuit on host arrays through the planner's
+// programs.  Returns 0 on success, otherwise a qf_status with qfc_last_error().
+int qfc_run(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tuning, const float* theta,
+            const float* x, const float* dE, float* E, float* dtheta, float* dx) {
+  try {
+    std::string msg;
+    qf_status st = validate_circuit(desc, &msg);
+    if (st != QF_OK) { g_err = msg; return st; }
+    Circuit C;
+    C.n = desc->n_qubits; C.P = desc->n_params; C.F = desc->n_inputs; C.K = desc->n_obs;
+    C.gates.assign(desc->gates, desc->gates + desc->n_gates);
+    C.obs.assign(desc->obs, desc->obs + desc->n_obs);
+    Tuning T;
+    if (tuning) {
+      T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
+      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt;
+    }
+    PlanCore pc;
+    st = build_plan_core(C, batch, T, &pc, &msg);
+    if (st != QF_OK) { g_err = msg; return st; }
+    std::vector<char> ws(pc.ws_bytes + 256, 0);
+    char* base = ws.data();
+    CpuExec ex(pc);
+    ex.ws_lo = base;
+    ex.ws_hi = base + pc.ws_bytes;
+    run_forward(pc, ex, theta, x, E, base);
+    if (dE) run_backward(pc, ex, theta, x, dE, dtheta, dx, base);
+    return 0;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return QF_ERR_INTERNAL;
+  }
+}
+
+// Schedule statistics: passes, segments, ops, layout count.
+int qfc_stats(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tuning, int64_t* out, int n_out) {
+  std::string msg;
+  qf_status st = validate_circuit(desc, &msg);
+  if (st != QF_OK) { g_err = msg; return st; }
+  Circuit C;
+  C.n = desc->n_qubits; C.P = desc->n_params; C.F = desc->n_inputs; C.K = desc->n_obs;
+  C.gates.assign(desc->gates, desc->gates + desc->n_gates);
+  C.obs.assign(desc->obs, desc->obs + desc->n_obs);
+  Tuning T;
+  if (tuning) {
+    T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
+    T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt;
+  }
+  PlanCore pc;
+  st = build_plan_core(C, batch, T, &pc, &msg);
+  if (st != QF_OK) { g_err = msg; return st; }
+  int64_t v[12] = {pc.P, pc.n_seg, pc.ckpt, pc.mb, pc.S.n_perm, pc.S.n_u2, pc.S.n_cz, (int64_t)pc.S.layouts.size(),
+                   (int64_t)pc.S.runs.size(), pc.S.k, pc.S.R, (int64_t)pc.ws_bytes};
+  for (int i = 0; i < n_out && i < 12; ++i) out[i] = v[i];
+  return 0;
+}
+
+const char* qfc_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

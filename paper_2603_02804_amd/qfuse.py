@@ -1,0 +1,260 @@
+"""Python binding of the C-ABI in include/qfuse.h (argument marshalling only).
+
+The functions ``qf_*`` below carry the C names and take the same arguments, with
+device buffers given as torch tensors (their data pointers are passed through).
+``Plan`` and ``CircuitFunction`` are conveniences built from them; every step of
+the simulation runs in the HIP library.  Importing this module does not load the
+library; the first call does, and fails loudly if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from .build import LIB
+
+QF_OK = 0
+_STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "workspace too small", 4: "out of memory",
+           5: "device error", 6: "internal error"}
+
+
+class QFuseError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+class qf_gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
+                ("theta_idx", ctypes.c_int32), ("input_idx", ctypes.c_int32)]
+
+
+class qf_pauli(ctypes.Structure):
+    _fields_ = [("x_mask", ctypes.c_uint64), ("z_mask", ctypes.c_uint64)]
+
+
+class qf_circuit_desc(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_params", ctypes.c_int32), ("n_inputs", ctypes.c_int32),
+                ("gates", ctypes.c_void_p), ("n_gates", ctypes.c_int64), ("obs", ctypes.c_void_p),
+                ("n_obs", ctypes.c_int32)]
+
+
+class qf_tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("mode", "tile_qubits", "reg_qubits", "fusion_depth",
+                                              "ckpt_interval", "micro_batch", "store_ckpt")]
+
+
+class qf_plan_info(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_int32) for n in ("n_qubits", "tile_qubits", "reg_qubits", "threads", "tiles",
+                                               "fused_passes", "segments", "ckpt_interval", "micro_batch",
+                                               "store_ckpt", "fusion_depth")]
+                + [("n_runs", ctypes.c_int64), ("n_perm", ctypes.c_int64), ("n_u2", ctypes.c_int64),
+                   ("n_cz", ctypes.c_int64)]
+                + [(n, ctypes.c_double) for n in ("fwd_bytes_per_sample", "bwd_bytes_per_sample",
+                                                  "fwd_flops_per_sample", "bwd_flops_per_sample",
+                                                  "bwd_pass_bytes_per_sample", "bwd_pass_flops_per_sample")]
+                + [("bwd_pass_launches", ctypes.c_int64)])
+
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """The HIP library; raises if it is missing (there is no other execution path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise FileNotFoundError(f"{LIB} is not built; run __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB)
+        P, I32, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        sigs = {
+            "qf_circuit_create": [P, P], "qf_circuit_destroy": [P],
+            "qf_plan_create": [P, I32, P, P], "qf_plan_destroy": [P], "qf_plan_get_info": [P, P],
+            "qf_workspace_size": [P, P],
+            "qf_forward": [P, P, P, P, P, SZ, P],
+            "qf_backward": [P, P, P, P, P, P, P, SZ, P],
+        }
+        for name, args in sigs.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        lib.qf_status_string.restype = ctypes.c_char_p
+        lib.qf_status_string.argtypes = [ctypes.c_int]
+        lib.qf_last_error.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != QF_OK:
+        raise QFuseError(status, library().qf_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------------- C names
+def qf_circuit_create(desc: qf_circuit_desc) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(library().qf_circuit_create(ctypes.byref(desc), ctypes.byref(h)))
+    return h
+
+
+def qf_circuit_destroy(circuit) -> None:
+    _check(library().qf_circuit_destroy(circuit))
+
+
+def qf_plan_create(circuit, batch: int, tuning: Optional[qf_tuning]) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(library().qf_plan_create(circuit, int(batch), ctypes.byref(tuning) if tuning else None, ctypes.byref(h)))
+    return h
+
+
+def qf_plan_destroy(plan) -> None:
+    _check(library().qf_plan_destroy(plan))
+
+
+def qf_plan_get_info(plan) -> qf_plan_info:
+    info = qf_plan_info()
+    _check(library().qf_plan_get_info(plan, ctypes.byref(info)))
+    return info
+
+
+def qf_workspace_size(plan) -> int:
+    n = ctypes.c_size_t()
+    _check(library().qf_workspace_size(plan, ctypes.byref(n)))
+    return int(n.value)
+
+
+def qf_forward(plan, theta: torch.Tensor, x: Optional[torch.Tensor], E: torch.Tensor, ws: torch.Tensor,
+               ws_bytes: int, stream) -> None:
+    _check(library().qf_forward(plan, _ptr(theta), _ptr(x), _ptr(E), _ptr(ws), ws_bytes, stream))
+
+
+def qf_backward(plan, theta: torch.Tensor, x: Optional[torch.Tensor], dE: torch.Tensor, dtheta: torch.Tensor,
+                dx: Optional[torch.Tensor], ws: torch.Tensor, ws_bytes: int, stream) -> None:
+    _check(library().qf_backward(plan, _ptr(theta), _ptr(x), _ptr(dE), _ptr(dtheta), _ptr(dx), _ptr(ws),
+                                 ws_bytes, stream))
+
+
+def qf_status_string(status: int) -> str:
+    return library().qf_status_string(status).decode()
+
+
+# --------------------------------------------------------------------- conveniences
+def make_tuning(mode=0, tile_qubits=0, reg_qubits=0, fusion_depth=0, ckpt_interval=0, micro_batch=0,
+                store_ckpt=-1) -> qf_tuning:
+    return qf_tuning(mode, tile_qubits, reg_qubits, fusion_depth, ckpt_interval, micro_batch, store_ckpt)
+
+
+class Circuit:
+    """Owns a qf_circuit built from int32 gate rows (kind, q0, q1, theta_idx, input_idx)."""
+
+    def __init__(self, n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequence[int],
+                 x_masks: Optional[Sequence[int]] = None):
+        self.gates = np.ascontiguousarray(gates, dtype=np.int32).reshape(-1, 5)
+        K = len(z_masks)
+        self.obs = np.zeros((K, 2), dtype=np.uint64)
+        self.obs[:, 1] = np.asarray(z_masks, dtype=np.uint64)
+        if x_masks is not None:
+            self.obs[:, 0] = np.asarray(x_masks, dtype=np.uint64)
+        self.n_qubits, self.n_params, self.n_inputs, self.n_obs = n_qubits, n_params, n_inputs, K
+        desc = qf_circuit_desc(n_qubits, n_params, n_inputs, self.gates.ctypes.data, len(self.gates),
+                               self.obs.ctypes.data if K else None, K)
+        self.handle = qf_circuit_create(desc)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.qf_circuit_destroy(h)
+            self.handle = None
+
+
+class Plan:
+    """A qf_plan for one batch size and tuning, plus its workspace."""
+
+    def __init__(self, circuit: Circuit, batch: int, tuning: Optional[qf_tuning] = None):
+        self.circuit = circuit
+        self.batch = int(batch)
+        self.handle = qf_plan_create(circuit.handle, self.batch, tuning)
+        self.ws_bytes = qf_workspace_size(self.handle)
+
+    @property
+    def info(self) -> qf_plan_info:
+        return qf_plan_get_info(self.handle)
+
+    def new_workspace(self, device=None) -> torch.Tensor:
+        return torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device or "cuda")
+
+    def _check_inputs(self, theta, x):
+        c = self.circuit
+        if theta.dtype != torch.float32 or not theta.is_cuda or theta.numel() != c.n_params:
+            raise ValueError("theta must be a float32 CUDA tensor of n_params elements")
+        if c.n_inputs:
+            if x is None or x.dtype != torch.float32 or not x.is_cuda or tuple(x.shape) != (self.batch, c.n_inputs):
+                raise ValueError("x must be a float32 CUDA tensor of shape [batch, n_inputs]")
+
+    def forward(self, theta: torch.Tensor, x: Optional[torch.Tensor], ws: torch.Tensor,
+                E: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._check_inputs(theta, x)
+        theta = theta.contiguous()
+        x = x.contiguous() if x is not None else None
+        if E is None:
+            E = torch.empty(self.batch, self.circuit.n_obs, dtype=torch.float32, device=theta.device)
+        qf_forward(self.handle, theta, x, E, ws, ws.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        return E
+
+    def backward(self, theta: torch.Tensor, x: Optional[torch.Tensor], dE: torch.Tensor, ws: torch.Tensor,
+                 want_dx: bool = True):
+        self._check_inputs(theta, x)
+        dE = dE.contiguous().to(torch.float32)
+        dtheta = torch.empty_like(theta)
+        dx = torch.empty_like(x) if (want_dx and x is not None) else None
+        qf_backward(self.handle, theta.contiguous(), x.contiguous() if x is not None else None, dE, dtheta, dx, ws,
+                    ws.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        return dtheta, dx
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.qf_plan_destroy(h)
+            self.handle = None
+
+
+class CircuitFunction(torch.autograd.Function):
+    """E = circuit(theta, x) with the fused adjoint backward.
+
+    The forward keeps the plan's workspace (segment checkpoints) alive in the
+    autograd context; the backward re-runs each segment from its checkpoint and
+    returns dL/dtheta (summed over the batch) and dL/dx (per sample).  Inputs are
+    never modified.
+    """
+
+    @staticmethod
+    def forward(ctx, theta, x, plan: Plan):
+        ws = plan.new_workspace(theta.device)
+        E = plan.forward(theta.detach(), x.detach() if x is not None else None, ws)
+        ctx.plan = plan
+        ctx.ws = ws
+        ctx.save_for_backward(theta, x if x is not None else torch.empty(0, device=theta.device))
+        ctx.has_x = x is not None
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        theta, x = ctx.saved_tensors
+        x = x if ctx.has_x else None
+        want_dx = ctx.has_x and ctx.needs_input_grad[1]
+        dtheta, dx = ctx.plan.backward(theta.detach(), x.detach() if x is not None else None, gE, ctx.ws,
+                                       want_dx=want_dx)
+        ctx.ws = None
+        return dtheta, dx, None
+
+
+def circuit_expectations(theta: torch.Tensor, x: Optional[torch.Tensor], plan: Plan) -> torch.Tensor:
+    return CircuitFunction.apply(theta, x, plan)

@@ -1,0 +1,85 @@
+"""ctypes binding of the test-only CPU schedule checker (libqfuse_plancheck.so)."""
+import ctypes
+import os
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2603_02804_amd", "libqfuse_plancheck.so")
+
+
+class Gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
+                ("theta_idx", ctypes.c_int32), ("input_idx", ctypes.c_int32)]
+
+
+class Pauli(ctypes.Structure):
+    _fields_ = [("x_mask", ctypes.c_uint64), ("z_mask", ctypes.c_uint64)]
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("n_qubits", ctypes.c_int32), ("n_params", ctypes.c_int32), ("n_inputs", ctypes.c_int32),
+                ("gates", ctypes.c_void_p), ("n_gates", ctypes.c_int64), ("obs", ctypes.c_void_p),
+                ("n_obs", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("mode", "tile_qubits", "reg_qubits", "fusion_depth",
+                                              "ckpt_interval", "micro_batch", "store_ckpt")]
+
+
+def make_tuning(**kw):
+    t = Tuning(0, 0, 0, 0, 0, 0, -1)
+    for k, v in kw.items():
+        setattr(t, k, v)
+    return t
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = ctypes.CDLL(LIB)
+        _lib.qfc_last_error.restype = ctypes.c_char_p
+    return _lib
+
+
+def _desc(n, gates, n_params, n_inputs, zmask):
+    gates = np.ascontiguousarray(gates, dtype=np.int32).reshape(-1, 5)
+    obs = np.zeros((len(zmask), 2), dtype=np.uint64)
+    obs[:, 1] = np.asarray(zmask, dtype=np.uint64)
+    d = Desc(n, n_params, n_inputs, gates.ctypes.data, len(gates), obs.ctypes.data, len(zmask))
+    return d, (gates, obs)
+
+
+def run(n, gates, theta, x, zmask, dE=None, **tuning):
+    theta = np.ascontiguousarray(theta, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    B = x.shape[0]
+    K = len(zmask)
+    d, keep = _desc(n, gates, len(theta), x.shape[1], zmask)
+    t = make_tuning(**tuning)
+    E = np.zeros((B, K), dtype=np.float32)
+    dth = np.zeros(len(theta), dtype=np.float32)
+    dx = np.zeros_like(x)
+    f = ctypes.c_void_p
+    dEa = None if dE is None else np.ascontiguousarray(dE, dtype=np.float32)
+    rc = lib().qfc_run(ctypes.byref(d), B, ctypes.byref(t), f(theta.ctypes.data), f(x.ctypes.data),
+                       f(dEa.ctypes.data) if dEa is not None else None, f(E.ctypes.data), f(dth.ctypes.data),
+                       f(dx.ctypes.data))
+    if rc != 0:
+        raise RuntimeError(f"qfc_run: {rc} {lib().qfc_last_error().decode()}")
+    return E, dth, dx
+
+
+def stats(n, gates, n_params, n_inputs, zmask, batch, **tuning):
+    d, keep = _desc(n, gates, n_params, n_inputs, zmask)
+    t = make_tuning(**tuning)
+    out = (ctypes.c_int64 * 12)()
+    rc = lib().qfc_stats(ctypes.byref(d), batch, ctypes.byref(t), out, 12)
+    if rc != 0:
+        raise RuntimeError(f"qfc_stats: {rc} {lib().qfc_last_error().decode()}")
+    keys = ["passes", "segments", "ckpt", "micro_batch", "perm", "u2", "cz", "layouts", "runs", "k", "R", "ws_bytes"]
+    return dict(zip(keys, list(out)))

@@ -1,0 +1,106 @@
+"""Planner and driver on the CPU: the fused programs, executed thread by thread by
+the test-only schedule checker (with bounds assertions on every LDS, state and
+partial-sum access), agree with the oracle for every configuration the GPU parity
+tests launch, and the schedules satisfy their structural invariants."""
+import numpy as np
+import pytest
+
+import plancheck as pc
+from oracle.oracle import Oracle
+from paper_2603_02804_amd.workloads import CZ, RX, RY, draw_inputs, hea_gates, z_observables
+
+E_TOL = 1e-4
+G_TOL = 1e-3
+
+SINGLE = [
+    (1, 3, ("RX", "RY", "RZ"), 3, {}),
+    (5, 3, ("RY", "RZ"), 5, {}),
+    (7, 4, ("RX", "RY", "RZ"), 3, {"fusion_depth": 2}),
+    (10, 3, ("RY", "RZ"), 4, {}),
+    (11, 3, ("RX", "RY", "RZ"), 3, {"fusion_depth": 1, "ckpt_interval": 2}),
+    (12, 5, ("RY", "RZ"), 6, {}),
+    (13, 3, ("RX", "RY", "RZ"), 2, {}),
+]
+MULTI = [
+    (9, 4, ("RY", "RZ"), 3, {"tile_qubits": 7, "reg_qubits": 2}),
+    (10, 5, ("RX", "RY", "RZ"), 3, {"tile_qubits": 8, "reg_qubits": 4, "ckpt_interval": 2, "micro_batch": 2}),
+    (12, 4, ("RX", "RY", "RZ"), 5, {"tile_qubits": 11, "fusion_depth": 2, "ckpt_interval": 3, "micro_batch": 2}),
+    (14, 3, ("RX", "RY", "RZ"), 3, {}),
+    (15, 4, ("RY", "RZ"), 2, {"store_ckpt": 0, "micro_batch": 1}),
+    (16, 3, ("RX", "RY", "RZ"), 2, {"fusion_depth": 8}),
+]
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return Oracle()
+
+
+def rel(a, b):
+    s = float(np.abs(b).max()) if np.size(b) else 0.0
+    d = float(np.abs(np.asarray(a, np.float64) - b).max()) if np.size(b) else 0.0
+    return d / s if s > 0 else d
+
+
+def check(orc, n, gates, theta, x, obs, seed=0, **tun):
+    xm, zm = z_observables(obs)
+    dE = np.random.default_rng(seed).normal(size=(x.shape[0], len(obs))).astype(np.float32)
+    E, dth, dx = pc.run(n, gates, theta, x, zm, dE, **tun)
+    Eo, dtho, dxo = orc.backward(n, gates, theta, x, xm, zm, dE)
+    assert np.abs(E - Eo).max() <= E_TOL
+    assert rel(dth, dtho) <= G_TOL
+    if x.shape[1]:
+        assert rel(dx, dxo) <= G_TOL
+
+
+@pytest.mark.parametrize("n,L,rots,B,tun", SINGLE + MULTI)
+def test_hea_programs(orc, n, L, rots, B, tun):
+    gates = hea_gates(n, L, rots)
+    theta, x, _ = draw_inputs(21, L * len(rots) * n, B, n)
+    obs = [0, n - 1] if n > 1 else [0]
+    if (n, L, rots, B, tun) in MULTI:
+        obs = [0, 3, n - 1]
+    check(orc, n, gates, theta, x, obs, **tun)
+
+
+@pytest.mark.parametrize("tun", [{}, {"tile_qubits": 8, "reg_qubits": 3, "fusion_depth": 2}, {"mode": 1}])
+def test_general_gate_list(orc, tun):
+    rng = np.random.default_rng(5)
+    n, B = 11, 3
+    rows = [(RY, q, -1, -1, q) for q in range(n)]
+    for _ in range(120):
+        k = int(rng.integers(0, 4))
+        q0 = int(rng.integers(0, n))
+        if k == CZ:
+            rows.append((CZ, q0, int((q0 + 1 + rng.integers(0, n - 1)) % n), -1, -1))
+        elif rng.random() < 0.15:
+            rows.append((k, q0, -1, -1, int(rng.integers(0, n))))
+        else:
+            rows.append((k, q0, -1, int(rng.integers(0, 40)), -1))
+    gates = np.asarray(rows, dtype=np.int32)
+    theta, x, _ = draw_inputs(9, 40, B, n)
+    check(orc, n, gates, theta, x, [0, 5, 10], **tun)
+
+
+def test_ring(orc):
+    gates = hea_gates(9, 3, ("RX", "RY", "RZ"), ring=True)
+    theta, x, _ = draw_inputs(3, 81, 4, 9)
+    check(orc, 9, gates, theta, x, [0, 4, 8], tile_qubits=7, reg_qubits=3)
+
+
+@pytest.mark.parametrize("n,L", [(6, 3), (11, 3)])
+def test_per_gate_programs(orc, n, L):
+    gates = hea_gates(n, L, ("RX", "RY", "RZ"))
+    theta, x, _ = draw_inputs(21, L * 3 * n, 3, n)
+    check(orc, n, gates, theta, x, [0, 2], mode=1)
+
+
+def test_schedule_shape_at_benchmark_sizes():
+    """20 qubits x 1000 layers: tiles of 2^13, register blocks of 5 qubits and
+    several layers fused per HBM round trip."""
+    g = hea_gates(20, 1000, ("RX", "RY", "RZ"))
+    st = pc.stats(20, g, 60000, 20, [1], 1000, fusion_depth=8)
+    assert st["k"] == 13 and st["R"] == 5
+    assert st["runs"] == 20 * 1000          # encoding merged into layer 1
+    assert st["u2"] == st["runs"]           # every run applied exactly once
+    assert st["passes"] < 1000              # more than one layer per pass on average
