@@ -1,0 +1,217 @@
+"""Benchmark: samples/s of forward + adjoint gradient on a 20-qubit, 1000-layer HEA.
+
+One step = forward to the expectations <Z_0..Z_9> of a batch of 1000 samples,
+10-class softmax cross-entropy in torch, and the fused adjoint backward to
+dL/dtheta (60000 angles, summed over the batch) and dL/dx (20 encoding angles
+per sample).  Inputs are resident in HBM before the timed region.
+
+Printed (one JSON line): throughput, the roofline position of the dominant
+kernel (the fused adjoint pass, timed live with HIP events around its launches),
+the unfused one-kernel-per-gate path on the same GPU, and the complex128 CPU
+oracle on the host cores (bounded sample, extrapolated).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "samples/s fwd+adjoint grad (20q×1000L HEA) fused vs per-gate; HBM GB/s % peak"
+PEAK_HBM_GBS = 8000.0
+# FP32 vector peak with the build's instruction set (packed FP32 disabled):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz.
+PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bwd_pass_hea20q1000l.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2603_02804_amd", "csrc", "qfuse.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=0, help="override the batch (exploration only)")
+    ap.add_argument("--layers", type=int, default=0, help="override the depth (exploration only)")
+    ap.add_argument("--fusion-depth", type=int, default=0)
+    ap.add_argument("--ckpt-interval", type=int, default=0)
+    ap.add_argument("--micro-batch", type=int, default=0)
+    ap.add_argument("--tile-qubits", type=int, default=0)
+    ap.add_argument("--no-baselines", action="store_true", help="skip the per-gate and CPU baselines")
+    ap.add_argument("--pg-samples", type=int, default=8)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration) and exit")
+    return ap.parse_args()
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def main() -> int:
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(samples are independent, so a multi-GPU run would shard the batch and all-reduce dL/dtheta)",
+              file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+    import torch.nn.functional as Fnn
+
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib << 20
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n}), flush=True)
+        return 0
+
+    from paper_2603_02804_amd import qfuse
+    from paper_2603_02804_amd.workloads import c4, make_workload
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.layers:
+        w = make_workload("hea20q", 20, args.layers, ("RX", "RY", "RZ"), 1000, tuple(range(10)), "ce", 4)
+    else:
+        w = c4()
+    B = args.batch or w.batch
+    x_np = w.x[:B]
+    lab_np = w.labels[:B]
+
+    tun = qfuse.make_tuning(fusion_depth=args.fusion_depth, ckpt_interval=args.ckpt_interval,
+                            micro_batch=args.micro_batch, tile_qubits=args.tile_qubits)
+    circ = qfuse.Circuit(w.n_qubits, w.gates, w.n_params, w.n_inputs, w.zmask)
+    plan = qfuse.Plan(circ, B, tun)
+    info = plan.info
+    theta = torch.tensor(w.theta, device=dev, requires_grad=True)
+    x = torch.tensor(x_np, device=dev, requires_grad=True)
+    labels = torch.tensor(lab_np, device=dev)
+
+    def step():
+        theta.grad = None
+        x.grad = None
+        E = qfuse.circuit_expectations(theta, x, plan)
+        loss = Fnn.cross_entropy(E, labels)
+        loss.backward()
+        return loss
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    qfuse.qf_profile_enable(plan.handle, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = qfuse.qf_profile_read(plan.handle)
+    qfuse.qf_profile_enable(plan.handle, False)
+    elapsed = t1 - t0
+    value = B * args.steps / elapsed
+    ms_step = 1000.0 * elapsed / args.steps
+
+    # dominant kernel: the fused adjoint pass
+    n_bwd = int(prof.launches[1])
+    bwd_s = prof.ms[1] / 1000.0
+    flops_bwd = info.bwd_pass_flops_per_sample * B * args.steps
+    bytes_bwd = info.bwd_pass_bytes_per_sample * B * args.steps
+    achieved_tf = flops_bwd / bwd_s / 1e12 if bwd_s > 0 else 0.0
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_src_sha") == kernel_sha() and tr.get("batch") == B and not args.layers:
+            traffic = tr.get("hbm_bytes_per_launch")
+    roofline = {
+        "kernel": "k_pass<5,256,bwd> (fused adjoint pass)",
+        "bound": "alu", "achieved": round(achieved_tf, 2), "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
+        "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+        "launches": n_bwd, "avg_launch_ms": round(prof.ms[1] / max(1, n_bwd), 4),
+        "flops_per_launch": flops_bwd / max(1, n_bwd), "bytes_per_launch": bytes_bwd / max(1, n_bwd),
+        "hbm_gbs": round(bytes_bwd / bwd_s / 1e9, 1) if bwd_s > 0 else 0.0,
+    }
+    step_bytes = (info.fwd_bytes_per_sample + info.bwd_bytes_per_sample) * B
+    hbm_gbs = step_bytes / (elapsed / args.steps) / 1e9
+    kernel_share = {"fwd_pass_ms": round(prof.ms[0] / args.steps, 1), "bwd_pass_ms": round(prof.ms[1] / args.steps, 1),
+                    "other_ms": round(prof.ms[2] / args.steps, 1)}
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"hea20q{w.n_layers}l: 20-qubit HEA, {w.n_layers} layers of RX,RY,RZ + CZ ladder, "
+                               f"{w.n_params} angles, RY encoding of 20 features, <Z_0..Z_9> -> 10-class CE",
+                   "batch": B, "micro_batch": info.micro_batch, "tile_qubits": info.tile_qubits,
+                   "fusion_depth": info.fusion_depth, "fused_passes": info.fused_passes,
+                   "ckpt_interval": info.ckpt_interval, "segments": info.segments},
+        "roofline": roofline,
+        "hbm": {"gbs": round(hbm_gbs, 1), "frac": round(hbm_gbs / PEAK_HBM_GBS, 4),
+                "bytes_per_sample": info.fwd_bytes_per_sample + info.bwd_bytes_per_sample},
+        "kernel_time_per_step": kernel_share,
+        "loss": float(loss.detach().cpu()),
+    }
+
+    if not args.no_baselines:
+        # unfused one-kernel-per-gate path on the same GPU (same circuit, full depth)
+        nb = min(args.pg_samples, B)
+        pg_plan = qfuse.Plan(circ, nb, qfuse.make_tuning(mode=1, micro_batch=nb))
+        th2 = theta.detach()
+        x2 = x.detach()[:nb].contiguous()
+        ws = pg_plan.new_workspace(dev)
+        lab2 = labels[:nb]
+
+        def pg_step():
+            E = pg_plan.forward(th2, x2, ws)
+            Ev = E.clone().requires_grad_(True)
+            Fnn.cross_entropy(Ev, lab2).backward()
+            pg_plan.backward(th2, x2, Ev.grad, ws)
+
+        pg_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pg_step()
+        torch.cuda.synchronize()
+        pg_s = time.perf_counter() - t0
+        pg_value = nb / pg_s
+        out["per_gate"] = {"value": round(pg_value, 3), "unit": "samples/s", "sample": f"{nb} samples, full depth",
+                           "speedup_fused": round(value / pg_value, 2)}
+        del ws
+        # CPU oracle on the host cores: one sample, the first L layers, extrapolated in depth
+        from oracle.oracle import Oracle, loss_and_grad_E
+        from paper_2603_02804_amd.workloads import hea_gates
+        orc = Oracle()
+        n = w.n_qubits
+
+        def cpu_time(L):
+            g = hea_gates(n, L, ("RX", "RY", "RZ"))
+            P = L * 3 * n
+            _, gE = loss_and_grad_E(np.zeros((1, w.n_obs)), "ce", lab_np[:1])
+            t = time.perf_counter()
+            orc.backward(n, g, w.theta[:P], x_np[:1], w.xmask, w.zmask, gE)
+            return time.perf_counter() - t
+
+        t1l = cpu_time(1)
+        Ls = int(max(1, min(w.n_layers, round(args.cpu_seconds / max(t1l, 1e-3)))))
+        tL = cpu_time(Ls) if Ls > 1 else t1l
+        per_sample = tL * w.n_layers / Ls
+        out["cpu_baseline"] = {"value": round(1.0 / per_sample, 6), "unit": "samples/s", "cores": orc.num_threads,
+                               "kind": "oracle",
+                               "sample": f"1 sample, first {Ls} of {w.n_layers} layers ({tL:.1f} s), "
+                                         f"extrapolated linearly in depth"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -146,6 +146,20 @@ qf_status qf_forward(qf_plan* plan, const float* theta, const float* x, float* E
 qf_status qf_backward(qf_plan* plan, const float* theta, const float* x, const float* dE,
                       float* dtheta, float* dx, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * Kernel timing for accounting.  While enabled, every launch the plan makes is
+ * bracketed by HIP events recorded on the call's stream; qf_profile_read waits
+ * for the recorded events, returns per-class launch counts and summed durations
+ * (milliseconds) since the last read, and clears them.  Classes: 0 = fused
+ * forward pass, 1 = fused adjoint pass, 2 = every other kernel of the plan.
+ */
+typedef struct {
+  int64_t launches[3];
+  double ms[3];
+} qf_profile;
+qf_status qf_profile_enable(qf_plan* plan, int enable);
+qf_status qf_profile_read(qf_plan* plan, qf_profile* out);
+
 const char* qf_status_string(qf_status status);
 /* Detail of the last error on the calling thread ("" if none). */
 const char* qf_last_error(void);

@@ -205,7 +205,7 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
     if (msg) *msg = "tile needs more than 256 threads; raise reg_qubits or lower tile_qubits";
     return false;
   }
-  B.F = T.fusion > 0 ? T.fusion : (n <= B.k ? 16 : 4);
+  B.F = T.fusion > 0 ? T.fusion : (n <= B.k ? 16 : 8);
   S.n = n;
   S.k = B.k;
   S.R = B.R;

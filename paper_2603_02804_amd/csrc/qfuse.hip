@@ -785,10 +785,44 @@ static PassFn select_pass(int R, int NT, bool bwd) {
   }
 }
 
+// Event pairs bracketing launches while a plan's profiling is enabled.
+struct Profiler {
+  bool on = false;
+  std::vector<hipEvent_t> ev;          // pool, reused across reads
+  std::vector<int> kind;               // class of each recorded pair
+  size_t used = 0;                     // pairs recorded since the last read
+  hipEvent_t get(size_t i) {
+    while (ev.size() <= i) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ev.push_back(e);
+    }
+    return ev[i];
+  }
+  void begin(hipStream_t st) {
+    if (!on) return;
+    hipEvent_t e = get(2 * used);
+    if (e) (void)hipEventRecord(e, st);
+  }
+  void end(hipStream_t st, int k) {
+    if (!on) return;
+    hipEvent_t e = get(2 * used + 1);
+    if (e) (void)hipEventRecord(e, st);
+    if (kind.size() <= used) kind.resize(used + 1);
+    kind[used++] = k;
+  }
+  ~Profiler() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 struct GpuExec {
   const PlanCore& c;
   const DevPlan& d;
   hipStream_t st;
+  Profiler* prof = nullptr;
+  void pb() { if (prof) prof->begin(st); }
+  void pe(int k) { if (prof) prof->end(st, k); }
   const float* theta = nullptr;
   const float* x = nullptr;
   const float* csh = nullptr;
@@ -811,8 +845,10 @@ struct GpuExec {
     theta = th; x = xx; csh = cs; cps = cp;
     const long long total = c.S.n_coef_shared + (long long)c.S.n_coef_ps * c.B;
     if (total == 0) return;
+    pb();
     hipLaunchKernelGGL(k_coef, dim3(blocks_for(total)), dim3(256), 0, st, d.tabs, th, xx, c.C.F, c.S.n_coef_shared,
                        c.S.n_coef_ps, c.B, cs, cp);
+    pe(2);
     check("k_coef");
   }
 
@@ -850,35 +886,45 @@ struct GpuExec {
       return;
     }
     const size_t shmem = sizeof(float2) << S.k;
+    pb();
     hipLaunchKernelGGL(fn, dim3((unsigned)((long long)L.nb << S.tiles_log2)), dim3(S.NT), shmem, st, A);
+    pe(L.bwd ? 1 : 0);
     check(L.bwd ? "k_pass(bwd)" : "k_pass(fwd)");
   }
 
   void reduce_E(int nb, int sample0, const float* partE, float* E) {
+    pb();
     hipLaunchKernelGGL(k_reduce_E, dim3(blocks_for((long long)nb * c.C.K)), dim3(256), 0, st, nb, sample0,
                        c.tiles * c.waves, c.C.K, partE, E);
+    pe(2);
     check("k_reduce_E");
   }
 
   void assemble(int seg, int nb, int sample0, const float* th, const float* xx, const float* partF, float* Gr) {
     const long long nr = (long long)(c.seg_run_begin[seg + 1] - c.seg_run_begin[seg]) * nb;
     if (nr == 0) return;
+    pb();
     hipLaunchKernelGGL(k_assemble, dim3(blocks_for(nr, 128)), dim3(128), 0, st, d.tabs, seg, nb, sample0,
                        c.tiles * c.waves, c.n_angle, th, xx, c.C.F, partF, Gr);
+    pe(2);
     check("k_assemble");
   }
 
   void reduce_grads(int nb, int sample0, const float* Gr, float* dtheta, float* dx, bool accumulate) {
     const long long total = c.C.P + (long long)nb * c.C.F;
     if (total == 0) return;
+    pb();
     hipLaunchKernelGGL(k_reduce_grads, dim3(blocks_for(total)), dim3(256), 0, st, d.tabs, nb, sample0, c.n_angle,
                        c.C.P, c.C.F, Gr, dtheta, dx, accumulate ? 1 : 0);
+    pe(2);
     check("k_reduce_grads");
   }
 
   // per-gate baseline
   void pg_init(float* psi, int nb) {
+    pb();
     hipLaunchKernelGGL(k_pg_init, dim3(blocks_for(c.amps * nb)), dim3(256), 0, st, (float2*)psi, (long long)c.amps, nb);
+    pe(2);
     check("k_pg_init");
   }
   void pg_copy(float* dst, const float* src, int nb) {
@@ -888,40 +934,54 @@ struct GpuExec {
     }
   }
   void pg_rot(float* psi, int nb, int sample0, int r, const float* cs, const float* cp) {
+    pb();
     hipLaunchKernelGGL(k_pg_rot, dim3(nb * c.pg_blocks), dim3(kPgThreads), 0, st, (float2*)psi, (long long)c.amps,
                        c.S.runs[r].q, c.S.runs[r].coef, sample0, cs, cp, c.S.n_coef_ps, c.pg_blocks);
+    pe(2);
     check("k_pg_rot");
   }
   void pg_cz(float* psi, float* lam, int nb, int qa, int qb) {
+    pb();
     hipLaunchKernelGGL(k_pg_cz, dim3(blocks_for((c.amps >> 2) * nb)), dim3(256), 0, st, (float2*)psi, (float2*)lam,
                        (long long)c.amps, qa, qb, nb);
+    pe(2);
     check("k_pg_cz");
   }
   void pg_expect(const float* psi, int nb, float* partE) {
+    pb();
     hipLaunchKernelGGL(k_pg_expect, dim3(nb * c.pg_blocks), dim3(kPgThreads), 0, st, (const float2*)psi,
                        (long long)c.amps, c.C.K, d.zmask, partE, c.pg_blocks);
+    pe(2);
     check("k_pg_expect");
   }
   void pg_reduce_E(int nb, int sample0, const float* partE, float* E) {
+    pb();
     hipLaunchKernelGGL(k_reduce_E, dim3(blocks_for((long long)nb * c.C.K)), dim3(256), 0, st, nb, sample0,
                        c.pg_blocks, c.C.K, partE, E);
+    pe(2);
     check("k_reduce_E");
   }
   void pg_seed(const float* psi, float* lam, int nb, int sample0, const float* dE) {
+    pb();
     hipLaunchKernelGGL(k_pg_seed, dim3(blocks_for(c.amps * nb)), dim3(256), 0, st, (const float2*)psi, (float2*)lam,
                        (long long)c.amps, nb, sample0, c.C.K, d.zmask, dE);
+    pe(2);
     check("k_pg_seed");
   }
   void pg_rot_bwd(float* psi, float* lam, int nb, int sample0, int r, int slot, const float* cs, const float* cp,
                   float* partF) {
+    pb();
     hipLaunchKernelGGL(k_pg_rot_bwd, dim3(nb * c.pg_blocks), dim3(kPgThreads), 0, st, (float2*)psi, (float2*)lam,
                        (long long)c.amps, c.S.runs[r].q, c.S.runs[r].coef, sample0, cs, cp, c.S.n_coef_ps, c.pg_blocks,
                        c.pg_chunk, slot, partF);
+    pe(2);
     check("k_pg_rot_bwd");
   }
   void pg_assemble(int r0, int cnt, int nb, int sample0, const float* partF, float* Gr) {
+    pb();
     hipLaunchKernelGGL(k_pg_assemble, dim3(blocks_for((long long)cnt * nb, 128)), dim3(128), 0, st, d.tabs, r0, cnt,
                        nb, c.pg_chunk, c.pg_blocks, c.n_angle, theta, x, c.C.F, sample0, partF, Gr);
+    pe(2);
     check("k_pg_assemble");
   }
 };
@@ -941,6 +1001,7 @@ struct qf_plan {
   PlanCore core;
   DevPlan dev;
   int device = 0;
+  Profiler prof;
 };
 
 namespace {
@@ -1138,6 +1199,7 @@ qf_status qf_forward(qf_plan* p, const float* theta, const float* x, float* E, v
   const PlanCore& c = p->core;
   if (!E || (c.C.P > 0 && !theta) || (c.C.F > 0 && !x)) return fail(QF_ERR_INVALID_ARG, "NULL buffer");
   GpuExec ex(c, p->dev, (hipStream_t)stream);
+  ex.prof = &p->prof;
   st = run_forward(c, ex, theta, x, E, (char*)ws);
   if (st != QF_OK) return fail(st, ex.msg);
   return QF_OK;
@@ -1151,12 +1213,37 @@ qf_status qf_backward(qf_plan* p, const float* theta, const float* x, const floa
   if (!dE || (c.C.P > 0 && (!theta || !dtheta)) || (c.C.F > 0 && !x))
     return fail(QF_ERR_INVALID_ARG, "NULL buffer");
   GpuExec ex(c, p->dev, (hipStream_t)stream);
+  ex.prof = &p->prof;
   ex.theta = theta;
   ex.x = x;
   ex.csh = (const float*)((char*)ws + c.off_coef_sh);
   ex.cps = (const float*)((char*)ws + c.off_coef_ps);
   st = run_backward(c, ex, theta, x, dE, dtheta, dx, (char*)ws);
   if (st != QF_OK) return fail(st, ex.msg);
+  return QF_OK;
+}
+
+qf_status qf_profile_enable(qf_plan* p, int enable) {
+  if (!p) return fail(QF_ERR_INVALID_ARG, "plan is NULL");
+  p->prof.on = enable != 0;
+  p->prof.used = 0;
+  return QF_OK;
+}
+
+qf_status qf_profile_read(qf_plan* p, qf_profile* out) {
+  if (!p || !out) return fail(QF_ERR_INVALID_ARG, "NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  Profiler& pr = p->prof;
+  for (size_t i = 0; i < pr.used; ++i) {
+    hipEvent_t a = pr.ev[2 * i], b = pr.ev[2 * i + 1];
+    if (hipEventSynchronize(b) != hipSuccess) return fail(QF_ERR_DEVICE, "hipEventSynchronize failed");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return fail(QF_ERR_DEVICE, "hipEventElapsedTime failed");
+    const int k = pr.kind[i];
+    out->launches[k] += 1;
+    out->ms[k] += ms;
+  }
+  pr.used = 0;
   return QF_OK;
 }
 

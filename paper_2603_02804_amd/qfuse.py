@@ -60,6 +60,10 @@ class qf_plan_info(ctypes.Structure):
                 + [("bwd_pass_launches", ctypes.c_int64)])
 
 
+class qf_profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 3), ("ms", ctypes.c_double * 3)]
+
+
 _lib = None
 
 
@@ -77,6 +81,7 @@ def library() -> ctypes.CDLL:
             "qf_workspace_size": [P, P],
             "qf_forward": [P, P, P, P, P, SZ, P],
             "qf_backward": [P, P, P, P, P, P, P, SZ, P],
+            "qf_profile_enable": [P, ctypes.c_int], "qf_profile_read": [P, P],
         }
         for name, args in sigs.items():
             fn = getattr(lib, name)
@@ -140,6 +145,16 @@ def qf_backward(plan, theta: torch.Tensor, x: Optional[torch.Tensor], dE: torch.
                 dx: Optional[torch.Tensor], ws: torch.Tensor, ws_bytes: int, stream) -> None:
     _check(library().qf_backward(plan, _ptr(theta), _ptr(x), _ptr(dE), _ptr(dtheta), _ptr(dx), _ptr(ws),
                                  ws_bytes, stream))
+
+
+def qf_profile_enable(plan, enable: bool) -> None:
+    _check(library().qf_profile_enable(plan, 1 if enable else 0))
+
+
+def qf_profile_read(plan) -> qf_profile:
+    out = qf_profile()
+    _check(library().qf_profile_read(plan, ctypes.byref(out)))
+    return out
 
 
 def qf_status_string(status: int) -> str:
