@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--ckpt-interval", type=int, default=0)
     ap.add_argument("--micro-batch", type=int, default=0)
     ap.add_argument("--tile-qubits", type=int, default=0)
+    ap.add_argument("--reg-qubits", type=int, default=0)
     ap.add_argument("--no-baselines", action="store_true", help="skip the per-gate and CPU baselines")
     ap.add_argument("--pg-samples", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -90,7 +91,8 @@ def main() -> int:
     lab_np = w.labels[:B]
 
     tun = qfuse.make_tuning(fusion_depth=args.fusion_depth, ckpt_interval=args.ckpt_interval,
-                            micro_batch=args.micro_batch, tile_qubits=args.tile_qubits)
+                            micro_batch=args.micro_batch, tile_qubits=args.tile_qubits,
+                            reg_qubits=args.reg_qubits)
     circ = qfuse.Circuit(w.n_qubits, w.gates, w.n_params, w.n_inputs, w.zmask)
     plan = qfuse.Plan(circ, B, tun)
     info = plan.info

@@ -30,7 +30,7 @@ struct PassLaunch {
   const float* src0 = nullptr; int64_t src0_stride = 0;   // psi input  (interleaved complex)
   const float* src1 = nullptr; int64_t src1_stride = 0;   // lambda input
   float* dst = nullptr; int64_t dst_stride = 0;           // psi (fwd) or lambda (bwd) output
-  float* partF = nullptr;   // backward functional partial sums of this pass
+  float* partF = nullptr;   // backward functional partial sums of this pass: [sample][tile][slot][3]
   float* partE = nullptr;   // forward expectation partial sums
   const float* dE = nullptr;
   int do_expect = 0;
@@ -57,7 +57,8 @@ struct PlanCore {
   int pg_chunk = 0;                   // rotation gates per partial-sum chunk
   int pg_blocks = 0;                  // partial sums per sample per gate
   // workspace
-  size_t off_coef_sh = 0, off_coef_ps = 0, off_ckpt = 0, off_work = 0, off_seg = 0, off_lam = 0;
+  size_t off_coef_sh = 0, off_coef_ps = 0, off_ev_sh = 0, off_ev_ps = 0;
+  size_t off_ckpt = 0, off_work = 0, off_seg = 0, off_lam = 0;
   size_t off_partE = 0, off_partF = 0, off_Gr = 0, ws_bytes = 0;
 };
 
@@ -116,6 +117,8 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
     size_t off = 0;
     c.off_coef_sh = off; off = align_up(off + sizeof(float) * 8 * std::max(1, S.n_coef_shared));
     c.off_coef_ps = off; off = align_up(off + sizeof(float) * 8 * std::max<int64_t>(1, int64_t(B) * S.n_coef_ps));
+    c.off_ev_sh = off;   off = align_up(off + sizeof(float) * 2);
+    c.off_ev_ps = off;   off = align_up(off + sizeof(float) * 2);
     c.off_ckpt = off;    off = align_up(off + SB * B);            // final states of the batch
     c.off_lam = off;     off = align_up(off + SB * 2 * c.mb);     // psi copy + lambda
     c.off_partE = off;   off = align_up(off + sizeof(float) * std::max<int64_t>(1, int64_t(c.mb) * c.pg_blocks * C.K));
@@ -151,7 +154,7 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
     int64_t acc = 0;
     for (int p = c.seg_begin[s]; p < c.seg_begin[s + 1]; ++p) {
       c.partF_off[p] = acc;
-      acc += int64_t(c.tiles) * c.waves * 3 * S.passes[p].n_slots;
+      acc += int64_t(c.tiles) * 3 * S.passes[p].n_slots;
     }
     c.partF_seg_floats = std::max(c.partF_seg_floats, acc);
   }
@@ -172,6 +175,8 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
   const int nck = c.store ? B : c.mb;
   c.off_coef_sh = off; off = align_up(off + sizeof(float) * 8 * std::max(1, S.n_coef_shared));
   c.off_coef_ps = off; off = align_up(off + sizeof(float) * 8 * std::max<int64_t>(1, int64_t(B) * S.n_coef_ps));
+  c.off_ev_sh = off;   off = align_up(off + sizeof(float) * 2 * std::max(1, S.n_ev_shared));
+  c.off_ev_ps = off;   off = align_up(off + sizeof(float) * 2 * std::max<int64_t>(1, int64_t(B) * S.n_ev_ps));
   c.off_ckpt = off;    off = align_up(off + SB * size_t(nck) * c.n_seg);
   c.off_work = off;    off = align_up(off + SB * size_t(c.mb) * 2);
   c.off_seg = off;     off = align_up(off + SB * size_t(c.mb) * std::max(0, c.ckpt - 1));
@@ -199,7 +204,7 @@ qf_status run_forward_pg(const PlanCore& c, Exec& ex, const float* theta, const 
   const int64_t SA = 2 * c.amps;
   const float* csh = at<float>(ws, c.off_coef_sh);
   const float* cps = at<float>(ws, c.off_coef_ps);
-  ex.coef(theta, x, at<float>(ws, c.off_coef_sh), at<float>(ws, c.off_coef_ps));
+  ex.coef(theta, x, ws);
   for (int mb0 = 0; mb0 < c.B; mb0 += c.mb) {
     const int nb = std::min(c.mb, c.B - mb0);
     float* psi = at<float>(ws, c.off_ckpt) + int64_t(mb0) * SA;
@@ -287,7 +292,7 @@ template <class Exec>
 qf_status run_forward(const PlanCore& c, Exec& ex, const float* theta, const float* x, float* E, char* ws) {
   if (c.per_gate) return run_forward_pg(c, ex, theta, x, E, ws);
   const int64_t SA = 2 * c.amps;
-  ex.coef(theta, x, at<float>(ws, c.off_coef_sh), at<float>(ws, c.off_coef_ps));
+  ex.coef(theta, x, ws);
   for (int mb0 = 0; mb0 < c.B; mb0 += c.mb) {
     const int nb = std::min(c.mb, c.B - mb0);
     float* ck = at<float>(ws, c.off_ckpt) + (c.store ? int64_t(mb0) * c.n_seg * SA : 0);

@@ -147,18 +147,12 @@ LayoutRec make_layout(const std::vector<int>& reg_pos, const std::vector<int>& t
                       const std::vector<int>& local, const std::vector<int>* map, int R) {
   LayoutRec L;
   std::memset(&L, 0, sizeof(L));
-  for (int j = 0; j < kMaxR; ++j) L.reg_qubit[j] = (j < R) ? local[reg_pos[j]] : -1;
-  for (int jj = 0; jj < (1 << R); ++jj) {
-    uint32_t lds = 0, lg = 0, mem = 0;
-    for (int j = 0; j < R; ++j)
-      if ((jj >> j) & 1) {
-        lds ^= lds_swizzle(1u << reg_pos[j]);
-        lg |= 1u << local[reg_pos[j]];
-        if (map) mem |= 1u << (*map)[local[reg_pos[j]]];
-      }
-    L.lds_reg[jj] = lds;
-    L.log_reg[jj] = lg;
-    L.mem_reg[jj] = mem;
+  for (int j = 0; j < kMaxR; ++j) {
+    L.reg_qubit[j] = (j < R) ? local[reg_pos[j]] : -1;
+    if (j >= R) continue;
+    L.lds_reg[j] = lds_swizzle(1u << reg_pos[j]);
+    L.log_reg[j] = 1u << local[reg_pos[j]];
+    L.mem_reg[j] = map ? (1u << (*map)[local[reg_pos[j]]]) : 0u;
   }
   for (size_t b = 0; b < thr_pos.size(); ++b) {
     L.lds_thr[b] = lds_swizzle(1u << thr_pos[b]);
@@ -194,47 +188,138 @@ void build_gate_runs(const Circuit& c, Schedule* s) {
 bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string* msg) {
   Schedule& S = *Sp;
   S = Schedule{};
-  Builder B(C, S);
   const int n = C.n;
-  B.n = n;
-  int kmax = T.k > 0 ? std::min(T.k, kMaxTileQubits) : kMaxTileQubits;
-  B.k = std::min(n, kmax);
-  B.R = std::min(T.R > 0 ? std::min(T.R, kMaxR) : kMaxR, B.k);
-  B.tb = B.k - B.R;
-  if (B.tb > kMaxThreadBits) {
+  // default tile: 2^12 amplitudes, 4 register qubits per lane, 256 lanes; the
+  // adjoint kernel then holds psi and lambda in 64 VGPRs and keeps 3 waves per SIMD
+  const int k = std::min(n, T.k > 0 ? std::min(T.k, kMaxTileQubits) : kDefaultTileQubits);
+  const int R = std::min(T.R > 0 ? std::min(T.R, kMaxR) : kDefaultRegQubits, k);
+  const int tb = k - R;
+  if (tb > kMaxThreadBits) {
     if (msg) *msg = "tile needs more than 256 threads; raise reg_qubits or lower tile_qubits";
     return false;
   }
-  B.F = T.fusion > 0 ? T.fusion : (n <= B.k ? 16 : 8);
+  const int F = T.fusion > 0 ? T.fusion : (n <= k ? 16 : 8);
   S.n = n;
-  S.k = B.k;
-  S.R = B.R;
-  S.thread_bits = B.tb;
-  S.active = 1 << B.tb;
+  S.k = k;
+  S.R = R;
+  S.thread_bits = tb;
+  S.active = 1 << tb;
   S.NT = std::max(64, S.active);
-  S.tiles_log2 = n - B.k;
-  S.fusion = B.F;
-  build_runs(C, S, &B.units, &B.wire, false);
-  B.ptr.assign(n, 0);
-  B.depth.assign(n, 0);
-  B.remaining = (int64_t)B.units.size();
-  const int k = B.k, R = B.R, tb = B.tb, F = B.F;
-  const int ncore = std::min(4, k);
+  S.tiles_log2 = n - k;
+  S.fusion = F;
+  std::vector<Unit> units_unused;
+  std::vector<std::vector<int>> wire_unused;
+  build_runs(C, S, &units_unused, &wire_unused, false);
 
-  std::vector<int> in_map(n), local;
-  std::iota(in_map.begin(), in_map.end(), 0);
+  // ---- per-wire runs and the diagonal items between them
+  // gap g of wire q lies before the wire's run g (gap m_q follows its last run)
+  struct Item {
+    int kind;        // 0 phase, 1 cz
+    int q0, q1;      // qubits (q1 = -1 for a phase)
+    int g0, g1;      // gap on q0 / q1
+    int ev;          // phase event index (kind 0)
+    bool applied = false, released = false, trailing = false;
+  };
+  std::vector<std::vector<int>> wire_runs(n);
+  for (size_t r = 0; r < S.runs.size(); ++r) wire_runs[S.runs[r].q].push_back((int)r);
+  std::vector<Item> items;
+  std::vector<std::vector<std::vector<int>>> gap_items(n);
+  for (int q = 0; q < n; ++q) gap_items[q].resize(wire_runs[q].size() + 1);
+  {
+    // CZ gates: gap = number of runs of the wire started before the gate
+    std::vector<int> started(n, 0);
+    std::vector<char> open(n, 0);
+    for (const qf_gate& g : C.gates) {
+      if (g.kind == QF_CZ) {
+        Item it;
+        it.kind = 1;
+        it.q0 = g.q0;
+        it.q1 = g.q1;
+        it.g0 = started[g.q0];
+        it.g1 = started[g.q1];
+        it.ev = -1;
+        int id = (int)items.size();
+        items.push_back(it);
+        gap_items[g.q0][it.g0].push_back(id);
+        gap_items[g.q1][it.g1].push_back(id);
+        open[g.q0] = open[g.q1] = 0;
+      } else if (!open[g.q0]) {
+        open[g.q0] = 1;
+        started[g.q0]++;
+      }
+    }
+  }
+  // phase items: one per gap that borders a run
+  for (int q = 0; q < n; ++q) {
+    const int m = (int)wire_runs[q].size();
+    for (int g = 0; g <= m; ++g) {
+      if (m == 0) break;
+      EventRec er;
+      er.prev_ref = g > 0 ? S.runs[wire_runs[q][g - 1]].coef : INT32_MIN;
+      er.next_ref = g < m ? S.runs[wire_runs[q][g]].coef : INT32_MIN;
+      er.per_sample = (er.prev_ref != INT32_MIN && er.prev_ref < 0) || (er.next_ref != INT32_MIN && er.next_ref < 0);
+      er.pad = 0;
+      int ref = er.per_sample ? -1 - (S.n_ev_ps++) : (S.n_ev_shared++);
+      Item it;
+      it.kind = 0;
+      it.q0 = q;
+      it.q1 = -1;
+      it.g0 = g;
+      it.g1 = -1;
+      it.ev = (int)S.pev.size();
+      S.pev.push_back({q, ref});
+      S.events.push_back(er);
+      int id = (int)items.size();
+      items.push_back(it);
+      gap_items[q][g].push_back(id);
+    }
+  }
+  // event table order: shared rows first, then per-sample rows, each by ref
+  {
+    std::vector<EventRec> ord(S.events.size());
+    std::vector<int> sh, ps;
+    for (size_t i = 0; i < S.pev.size(); ++i) (S.pev[i].ref >= 0 ? sh : ps).push_back((int)i);
+    size_t o = 0;
+    for (int i : sh) ord[o++] = S.events[i];
+    for (int i : ps) ord[o++] = S.events[i];
+    S.events = ord;   // shared rows 0..n_ev_shared-1, per-sample rows after
+  }
+  for (Item& it : items) {
+    const int m0 = (int)wire_runs[it.q0].size();
+    it.trailing = it.g0 == m0 && (it.kind == 0 || it.g1 == (int)wire_runs[it.q1].size());
+  }
 
-  // priority: the wire of the earliest pending run in circuit order (which is
-  // always ready once ready CZs are applied, so every pass makes progress), then
-  // wires with pending units, least advanced first
+  std::vector<int> runs_done(n, 0);
+  int64_t runs_left = (int64_t)S.runs.size();
+  std::vector<int> released_list;
+  auto try_release = [&](int id) {
+    Item& it = items[id];
+    if (it.released || it.applied || it.trailing) return;
+    if (runs_done[it.q0] < it.g0) return;
+    if (it.kind == 1 && runs_done[it.q1] < it.g1) return;
+    it.released = true;
+    released_list.push_back(id);
+  };
+  for (size_t i = 0; i < items.size(); ++i) try_release((int)i);
+  auto gap_clear = [&](int q) {   // all items before the wire's next run applied
+    for (int id : gap_items[q][runs_done[q]])
+      if (!items[id].applied) return false;
+    return true;
+  };
+  auto gap_released = [&](int q) {
+    for (int id : gap_items[q][runs_done[q]])
+      if (!items[id].applied && !items[id].released) return false;
+    return true;
+  };
+  auto has_run = [&](int q) { return runs_done[q] < (int)wire_runs[q].size(); };
+
+  // ---- priority (see the scheduling notes in the header)
   auto earliest_run_wire = [&]() {
     int best = -1, bo = 0;
     for (int q = 0; q < n; ++q) {
-      int u = B.front(q);
-      if (u >= 0 && B.units[u].kind == 0 && (best < 0 || B.units[u].order < bo)) {
-        best = q;
-        bo = B.units[u].order;
-      }
+      if (!has_run(q)) continue;
+      const int gi = S.run_gates[S.runs[wire_runs[q][runs_done[q]]].gate_begin];
+      if (best < 0 || gi < bo) { best = q; bo = gi; }
     }
     return best;
   };
@@ -242,17 +327,18 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
     const int first = earliest_run_wire();
     std::stable_sort(qs.begin(), qs.end(), [&](int a, int b) {
       if ((a == first) != (b == first)) return a == first;
-      bool pa = B.front(a) >= 0, pb = B.front(b) >= 0;
+      bool pa = has_run(a), pb = has_run(b);
       if (pa != pb) return pa;
-      if (B.depth[a] != B.depth[b]) return B.depth[a] < B.depth[b];
+      if (runs_done[a] != runs_done[b]) return runs_done[a] < runs_done[b];
       return a < b;
     });
     return qs;
   };
   std::vector<int> all(n);
   std::iota(all.begin(), all.end(), 0);
-
-  // initial local set: memory core + least advanced
+  const int ncore = std::min(4, k);
+  std::vector<int> in_map(n), local;
+  std::iota(in_map.begin(), in_map.end(), 0);
   if (n <= k) {
     local = all;
   } else {
@@ -264,7 +350,7 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
   }
 
   int pass_id = 0;
-  const int64_t guard = (int64_t)B.units.size() * 4 + 16;
+  const int64_t guard = (int64_t)S.runs.size() * 4 + (int64_t)items.size() + 16;
   while (true) {
     if (pass_id > guard) {
       if (msg) *msg = "scheduler made no progress";
@@ -272,16 +358,15 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
     }
     PassRec pr;
     std::memset(&pr, 0, sizeof(pr));
-    // tile positions: in-memory order of the local qubits (core first)
     std::sort(local.begin(), local.end(), [&](int a, int b) { return in_map[a] < in_map[b]; });
     std::vector<int> pos_of(n, -1);
     for (int p = 0; p < k; ++p) pos_of[local[p]] = p;
     {
-      int i = 0;
       std::vector<int> nl;
       for (int q = 0; q < n; ++q)
         if (pos_of[q] < 0) nl.push_back(q);
       std::sort(nl.begin(), nl.end(), [&](int a, int b) { return in_map[a] < in_map[b]; });
+      int i = 0;
       for (int q : nl) {
         pr.nl_log[i] = (uint8_t)q;
         pr.nl_in[i] = (uint8_t)in_map[q];
@@ -289,7 +374,6 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
       }
       pr.n_nonlocal = i;
     }
-    // load layout: lanes on the lowest memory bits
     auto io_layout = [&](const std::vector<int>& map) {
       std::vector<int> by_mem(k);
       std::iota(by_mem.begin(), by_mem.end(), 0);
@@ -302,111 +386,146 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
     };
     const int fop_begin = (int)S.ops.size();
     int cur = io_layout(in_map);
-    S.ops.push_back({pass_id == 0 ? OP_INIT0 : OP_LOAD, cur, 0, 0});
-    std::vector<int> regq(R, -1);   // qubit in each register bit of `cur` (unknown for io)
-    for (int j = 0; j < R; ++j) regq[j] = S.layouts[cur].reg_qubit[j];
+    S.ops.push_back({pass_id == 0 ? OP_INIT0 : OP_LOAD, cur, 0, 0, 0, 0, 0, 0});
+    std::vector<int> regq(R);
+    auto set_regs = [&]() {
+      for (int j = 0; j < R; ++j) regq[j] = S.layouts[cur].reg_qubit[j];
+    };
+    set_regs();
+    auto is_reg = [&](int q) { return std::find(regq.begin(), regq.end(), q) != regq.end(); };
     std::vector<int> pass_runs(n, 0);
     int slot = 0;
 
-    auto apply_ready_czs = [&]() {
+    // diagonal items whose qubits are all outside the register bits: one factor per thread
+    auto apply_free = [&]() {
       std::map<int, uint32_t> groups;
-      bool found = true;
-      while (found) {
-        found = false;
-        for (int q = 0; q < n; ++q) {
-          int u = B.front(q);
-          if (u < 0 || B.units[u].kind != 1 || B.units[u].a != q || !B.ready(u)) continue;
-          int lo = std::min(B.units[u].a, B.units[u].b), hi = std::max(B.units[u].a, B.units[u].b);
-          groups[hi - lo] ^= 1u << lo;   // CZ twice on the same pair cancels
-          B.finish(u);
-          found = true;
+      std::vector<PhaseEv> evs;
+      std::vector<int> keep;
+      for (int id : released_list) {
+        Item& it = items[id];
+        if (it.applied) continue;
+        if (is_reg(it.q0) || (it.kind == 1 && is_reg(it.q1))) {
+          keep.push_back(id);
+          continue;
         }
+        it.applied = true;
+        if (it.kind == 1) {
+          int lo = std::min(it.q0, it.q1), hi = std::max(it.q0, it.q1);
+          groups[hi - lo] ^= 1u << lo;
+        } else {
+          evs.push_back(S.pev[it.ev]);
+        }
+        S.n_diag_thread++;
       }
+      released_list = keep;
       std::vector<CzGroup> gs;
       for (auto& kv : groups)
         if (kv.second) gs.push_back({(uint32_t)kv.first, kv.second});
-      if (!gs.empty()) {
-        S.ops.push_back({OP_CZ, cur, (int32_t)S.czg.size(), (int32_t)gs.size()});
-        for (auto& g : gs) S.czg.push_back(g);
-        S.n_cz++;
-      }
-    };
-    auto runnable = [&](int q) {
-      int u = B.front(q);
-      return u >= 0 && B.units[u].kind == 0 && pass_runs[q] < F;
+      if (gs.empty() && evs.empty()) return;
+      const int cb = (int)S.czg.size(), eb = (int)S.pev.size();
+      for (auto& g : gs) S.czg.push_back(g);
+      for (auto& e : evs) S.pev.push_back(e);
+      S.ops.push_back({OP_DIAGT, cur, cb, (int)gs.size(), eb, (int)evs.size(), 0, 0});
     };
 
     while (true) {
-      apply_ready_czs();
+      apply_free();
       std::vector<int> cands;
       for (int q : local)
-        if (runnable(q)) cands.push_back(q);
+        if (has_run(q) && pass_runs[q] < F && gap_released(q)) cands.push_back(q);
       if (cands.empty()) break;
+      // wires whose items are all applied first (no per-amplitude work), then priority
       cands = by_priority(cands);
-      // register set: ready runs first, then local wires whose next run waits on a CZ
+      std::stable_sort(cands.begin(), cands.end(), [&](int a, int b) { return gap_clear(a) > gap_clear(b); });
       std::vector<int> want(cands.begin(), cands.begin() + std::min<size_t>(R, cands.size()));
+      const int n_run_wires = (int)want.size();
       if ((int)want.size() < R) {
         std::vector<int> others;
         for (int q : local)
-          if (std::find(want.begin(), want.end(), q) == want.end() && B.front(q) >= 0 && pass_runs[q] < F)
-            others.push_back(q);
+          if (std::find(want.begin(), want.end(), q) == want.end()) others.push_back(q);
         others = by_priority(others);
         for (int q : others)
           if ((int)want.size() < R) want.push_back(q);
       }
       bool same = true;
       for (int q : want)
-        if (std::find(regq.begin(), regq.end(), q) == regq.end()) same = false;
+        if (!is_reg(q)) same = false;
       if (!same) {
-        // fill the register bits, then order the thread positions
         std::vector<int> reg;
         for (int q : want) reg.push_back(pos_of[q]);
         std::vector<int> free_pos;
         for (int p = 0; p < k; ++p)
           if (std::find(reg.begin(), reg.end(), p) == reg.end()) free_pos.push_back(p);
-        // fillers: prefer residues mod 4 with the most free positions left
-        while ((int)reg.size() < R) {
-          int cnt[4] = {0, 0, 0, 0};
-          for (int p : free_pos) cnt[p & 3]++;
-          int best = 0;
-          for (int i = 1; i < (int)free_pos.size(); ++i)
-            if (cnt[free_pos[i] & 3] > cnt[free_pos[best] & 3]) best = i;
-          reg.push_back(free_pos[best]);
-          free_pos.erase(free_pos.begin() + best);
-        }
         std::vector<int> thr = order_thread_positions(free_pos, tb);
         int id = (int)S.layouts.size();
         S.layouts.push_back(make_layout(reg, thr, local, nullptr, R));
-        S.ops.push_back({OP_PERM, cur, id, 0});
+        S.ops.push_back({OP_PERM, cur, id, 0, 0, 0, 0, 0});
         S.n_perm++;
         cur = id;
-        for (int j = 0; j < R; ++j) regq[j] = S.layouts[cur].reg_qubit[j];
+        set_regs();
+        apply_free();
       }
-      bool progress = true;
-      while (progress) {
-        progress = false;
-        for (int j = 0; j < R; ++j) {
-          int q = regq[j];
-          if (q < 0 || !runnable(q)) continue;
-          int u = B.front(q);
-          int r = B.units[u].run;
-          RunRec& rr = S.runs[r];
-          rr.pass = pass_id;
-          rr.slot = slot++;
-          S.ops.push_back({OP_U2, j, rr.coef, r});
-          S.n_u2++;
-          B.finish(u);
-          pass_runs[q]++;
-          progress = true;
+      // items that still block the chosen runs touch register bits: per amplitude
+      std::vector<std::pair<int, int>> edges;
+      std::vector<int> run_wires(want.begin(), want.begin() + n_run_wires);
+      for (int q : run_wires)
+        for (int id : gap_items[q][runs_done[q]]) {
+          Item& it = items[id];
+          if (it.applied) continue;
+          it.applied = true;
+          S.n_diag_amp++;
+          if (it.kind == 1) {
+            edges.push_back({it.q0, it.q1});
+          } else {
+            int j = (int)(std::find(regq.begin(), regq.end(), q) - regq.begin());
+            const int eb = (int)S.pev.size();
+            S.pev.push_back(S.pev[it.ev]);
+            S.ops.push_back({OP_PHASEA, j, eb, 0, 0, 0, 0, 0});
+          }
         }
-        if (progress) apply_ready_czs();
+      if (!edges.empty()) {
+        CzaRec cr;
+        std::memset(&cr, 0, sizeof(cr));
+        std::vector<int> rb(n, -1);
+        for (int j = 0; j < R; ++j) rb[regq[j]] = j;
+        for (auto& e : edges) {
+          const int ja = rb[e.first], jbb = rb[e.second];
+          if (ja >= 0 && jbb >= 0) {
+            for (int jj = 0; jj < (1 << R); ++jj)
+              if (((jj >> ja) & 1) && ((jj >> jbb) & 1)) cr.sr ^= 1u << jj;
+          } else if (ja >= 0) {
+            cr.cmask[ja] ^= 1u << e.second;
+          } else {
+            cr.cmask[jbb] ^= 1u << e.first;
+          }
+        }
+        S.ops.push_back({OP_CZA, (int)S.cza.size(), cur, 0, 0, 0, 0, 0});
+        S.cza.push_back(cr);
+        S.n_cz++;
+      }
+      for (int j = 0; j < R; ++j) {
+        const int q = regq[j];
+        if (std::find(run_wires.begin(), run_wires.end(), q) == run_wires.end()) continue;
+        const int r = wire_runs[q][runs_done[q]];
+        RunRec& rr = S.runs[r];
+        rr.pass = pass_id;
+        rr.slot = slot++;
+        S.ops.push_back({OP_RY, j, rr.coef, r, 0, 0, 0, 0});
+        S.n_u2++;
+        runs_done[q]++;
+        runs_left--;
+        pass_runs[q]++;
+        for (int id : gap_items[q][runs_done[q]]) try_release(id);
       }
     }
     pr.n_slots = slot;
-    const bool last = (B.remaining == 0);
-    if (last) S.ops.push_back({OP_EXPECT, cur, 0, 0});
+    const bool last = (runs_left == 0);
+    if (last) {
+      // only trailing diagonal gates remain; they commute with the Z-string
+      // observables and change neither E nor the adjoint at the cuts
+      S.ops.push_back({OP_EXPECT, cur, 0, 0, 0, 0, 0, 0});
+    }
 
-    // next local set and the memory map after this pass
     std::vector<int> out_map(n);
     std::vector<int> next_local;
     if (n <= k) {
@@ -421,7 +540,6 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
         for (int q : next_local) c += in_cur(q);
         return c;
       };
-      // keep at least `ncore` qubits of this tile so both passes stream >=128-byte rows
       for (int q : pr_all) {
         if (cnt_overlap() >= ncore) break;
         if (!in_cur(q) || std::find(next_local.begin(), next_local.end(), q) != next_local.end()) continue;
@@ -431,7 +549,6 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
             break;
           }
       }
-      // memory core: shared qubits, distinct tile-position residues if possible
       std::vector<int> shared;
       for (int q : next_local)
         if (in_cur(q)) shared.push_back(q);
@@ -456,8 +573,11 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
     }
     for (int i = 0; i < pr.n_nonlocal; ++i) pr.nl_out[i] = (uint8_t)out_map[pr.nl_log[i]];
     int io_out = io_layout(out_map);
-    if (io_out != cur) S.ops.push_back({OP_PERM, cur, io_out, 0});
-    S.ops.push_back({OP_STORE, io_out, 0, 1});
+    S.ops.push_back({OP_PERM, cur, io_out, 0, 0, 0, 0, 0});
+    cur = io_out;
+    set_regs();
+    if (!last) apply_free();
+    S.ops.push_back({OP_STORE, io_out, 0, 1, 0, 0, 0, 0});
     pr.fop_begin = fop_begin;
     pr.fop_count = (int)S.ops.size() - fop_begin;
     S.passes.push_back(pr);
@@ -473,48 +593,55 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
     PassRec& pr = S.passes[p];
     std::vector<Op> f(S.ops.begin() + pr.fop_begin, S.ops.begin() + pr.fop_begin + pr.fop_count);
     std::vector<Op> b;
-    const Op& st = f.back();        // STORE with the output layout
-    const Op& ld = f.front();       // LOAD / INIT0 with the input layout
-    b.push_back({OP_LOAD, st.a, 0, 1});
-    if (p == P - 1) b.push_back({OP_SEED, st.a, 0, 0});
-    else b.push_back({OP_LOAD, st.a, 1, 1});
+    const Op st = f.back();
+    const Op ld = f.front();
+    b.push_back({OP_LOAD, st.a, 0, 1, 0, 0, 0, 0});
+    if (p == P - 1) b.push_back({OP_SEED, st.a, 0, 0, 0, 0, 0, 0});
+    else b.push_back({OP_LOAD, st.a, 1, 1, 0, 0, 0, 0});
     int i = (int)f.size() - 2;
     while (i >= 1) {
       const Op& o = f[i];
-      if (o.kind == OP_U2) {
-        // f[j..i]: consecutive runs on distinct register bits (distinct qubits,
-        // nothing in between), so their functionals share one cut
+      if (o.kind == OP_RY) {
+        // f[j..i]: runs of one register epoch on distinct qubits, nothing in
+        // between, so their functionals share one cut
         int j = i;
         uint32_t bits = 1u << f[i].a;
-        while (j - 1 >= 1 && f[j - 1].kind == OP_U2 && !((bits >> f[j - 1].a) & 1)) {
+        while (j - 1 >= 1 && f[j - 1].kind == OP_RY && !((bits >> f[j - 1].a) & 1)) {
           --j;
           bits |= 1u << f[j].a;
         }
         int fb = (int)S.funcs.size();
         for (int m = j; m <= i; ++m) S.funcs.push_back({f[m].a, S.runs[f[m].c].slot});
-        b.push_back({OP_FUNC, i - j + 1, fb, 0});
-        for (int m = i; m >= j; --m) b.push_back({OP_U2ADJ, f[m].a, f[m].b, f[m].c});
+        b.push_back({OP_FUNC, i - j + 1, fb, 0, 0, 0, 0, 0});
+        for (int m = i; m >= j; --m) b.push_back(f[m]);
         i = j - 1;
         continue;
       }
-      if (o.kind == OP_PERM) b.push_back({OP_PERM, o.b, o.a, 0});
-      else if (o.kind == OP_CZ) b.push_back(o);
-      // OP_EXPECT: nothing to undo
+      if (o.kind == OP_PERM) b.push_back({OP_PERM, o.b, o.a, 0, 0, 0, 0, 0});
+      else if (o.kind == OP_DIAGT || o.kind == OP_CZA || o.kind == OP_PHASEA) b.push_back(o);
       --i;
     }
-    if (p > 0) b.push_back({OP_STORE, ld.a, 0, 0});
+    if (p > 0) b.push_back({OP_STORE, ld.a, 0, 0, 0, 0, 0, 0});
     pr.bop_begin = (int)S.ops.size();
     pr.bop_count = (int)b.size();
     S.ops.insert(S.ops.end(), b.begin(), b.end());
   }
-  // sanity: every unit applied exactly once
-  if (B.remaining != 0) {
-    if (msg) *msg = "scheduler left gates unapplied";
+  if (runs_left != 0) {
+    if (msg) *msg = "scheduler left runs unapplied";
     return false;
   }
-  for (const RunRec& r : S.runs)
-    if (r.pass < 0) {
-      if (msg) *msg = "run without a pass";
+  // runs of each pass in slot order
+  S.pass_run_begin.assign(P + 1, 0);
+  for (const RunRec& r : S.runs) S.pass_run_begin[r.pass + 1]++;
+  for (int p = 0; p < P; ++p) S.pass_run_begin[p + 1] += S.pass_run_begin[p];
+  S.pass_runs.assign(S.runs.size(), 0);
+  for (size_t r = 0; r < S.runs.size(); ++r)
+    S.pass_runs[S.pass_run_begin[S.runs[r].pass] + S.runs[r].slot] = (int)r;
+  S.max_slots = 0;
+  for (const PassRec& pr : S.passes) S.max_slots = std::max(S.max_slots, pr.n_slots);
+  for (const Item& it : items)
+    if (!it.applied && !it.trailing) {
+      if (msg) *msg = "scheduler left a diagonal gate unapplied";
       return false;
     }
   return true;

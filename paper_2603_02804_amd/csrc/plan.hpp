@@ -50,8 +50,15 @@ struct Schedule {
   std::vector<LayoutRec> layouts;
   std::vector<CzGroup> czg;
   std::vector<FuncEntry> funcs;
+  std::vector<EventRec> events;       // phase event coefficient definitions
+  int n_ev_shared = 0, n_ev_ps = 0;
+  std::vector<PhaseEv> pev;           // phase events referenced by DIAGT / PHASEA ops
+  std::vector<CzaRec> cza;
+  std::vector<int32_t> pass_run_begin, pass_runs;   // runs of each pass, slot order
+  int max_slots = 0;
   // per-sample op counts over all forward passes
   int64_t n_perm = 0, n_u2 = 0, n_cz = 0;
+  int64_t n_diag_thread = 0, n_diag_amp = 0;   // diagonal items folded per thread / applied per amplitude
 };
 
 // Fused schedule.  Fails only on internal inconsistencies (the circuit is

@@ -19,38 +19,84 @@ constexpr int kMaxThreadBits = 8;  // up to 256 threads per workgroup
 constexpr int kMaxTileQubits = kMaxR + kMaxThreadBits;
 constexpr int kMaxQubits = 30;
 constexpr int kSwizzleBits = 4;    // LDS XOR swizzle folds 4-bit chunks
+constexpr int kDefaultTileQubits = 12;
+constexpr int kDefaultRegQubits = 4;
 
+// Ops of a pass program.  Every run (merged single-qubit rotations of one
+// qubit) is split as RZ(a) RY(b) RZ(c): only the real RY(b) touches amplitude
+// pairs; the RZ phases and the CZ signs are diagonal and are applied where they
+// are cheapest.  While all their qubits are held in thread bits (or are outside
+// the tile) they reduce to one complex factor per thread, accumulated in a
+// pending per-thread phase that is multiplied into the amplitudes at the next
+// PERM or STORE.  Otherwise they are applied per amplitude (CZA, PHASEA).
 enum OpKind : int32_t {
   OP_INIT0 = 1,   // a=layout: |0...0> restricted to the tile
   OP_LOAD = 2,    // a=layout, b=buffer (0 psi, 1 lambda), c=map (0 in, 1 out)
-  OP_STORE = 3,   // a=layout, b=buffer (0 = destination), c=map
-  OP_PERM = 4,    // a=from layout, b=to layout (psi, and lambda in the backward)
-  OP_U2 = 5,      // a=register bit, b=coefficient ref (>=0 shared, <0 per-sample -1-idx)
-  OP_U2ADJ = 6,   // same, applies u^dagger to psi and lambda
-  OP_CZ = 7,      // a=layout, b=first CZ group, c=number of groups
-  OP_EXPECT = 8,  // a=layout: Z-string expectations of psi -> partial sums
-  OP_SEED = 9,    // a=layout: lambda = 2 sum_k g_k O_k psi
-  OP_FUNC = 10,   // a=entries, b=first FuncEntry: Im<lambda|P_q|psi> for P=X,Y,Z
+  OP_STORE = 3,   // a=layout, c=map: flush the pending phase, write psi (fwd) / lambda (bwd)
+  OP_PERM = 4,    // a=from layout, b=to layout: flush the pending phase, exchange through LDS
+  OP_RY = 5,      // a=register bit, b=run coefficient ref (>=0 shared, <0 per-sample -1-idx),
+                  // c=run id; backward: RY(b)^dagger on psi and lambda
+  OP_DIAGT = 6,   // a=layout, b=first CZ group, c=groups, d=first phase event, e=events:
+                  // diagonal gates on thread-held qubits, folded into the pending phase
+  OP_CZA = 7,     // a=CzaRec, b=layout: CZ signs for edges touching register bits
+  OP_PHASEA = 8,  // a=register bit, b=phase event: RZ phase on a register-held qubit
+  OP_EXPECT = 9,  // a=layout: Z-string expectations of psi -> partial sums
+  OP_SEED = 10,   // a=layout: lambda = 2 sum_k g_k O_k psi
+  OP_FUNC = 11,   // a=entries, b=first FuncEntry: Im<lambda|P_q|psi> for P=X,Y,Z
 };
 
 struct Op {
-  int32_t kind, a, b, c;
+  int32_t kind, a, b, c, d, e, f, g;
 };
 
-// Uniform address tables of one layout.  Index of the amplitude held by thread
-// t in register slot jj:  T(t) ^ reg[jj] where T(t) = XOR of thr[i] over the set
-// bits i of t.  Three index spaces: LDS element (XOR-swizzled), logical basis
-// index (qubit q at bit q) and memory index (only for load / store layouts).
-struct LayoutRec {
-  uint32_t lds_reg[1 << kMaxR];
-  uint32_t lds_thr[kMaxThreadBits];
-  uint32_t log_reg[1 << kMaxR];
-  uint32_t log_thr[kMaxThreadBits];
-  uint32_t mem_reg[1 << kMaxR];
-  uint32_t mem_thr[kMaxThreadBits];
-  int32_t reg_qubit[kMaxR];   // logical qubit in register bit j (-1: none)
-  int32_t pad[3];
+// RZ phase on qubit q: amplitudes with bit q = 0 gain w, bit q = 1 gain conj(w);
+// w = e^{-i a_prev/2} e^{-i c_next/2} joins the trailing RZ of one run with the
+// leading RZ of the next run on the same qubit (only diagonal gates between).
+struct PhaseEv {
+  int32_t q;
+  int32_t ref;    // event coefficient: >=0 shared row, <0 per-sample row -1-idx
 };
+
+// Per-amplitude CZ signs on a register layout: sign(jj) = bit jj of sr XOR
+// parity over register bits j set in jj of parity(A & cmask[j]), A = the
+// thread's logical base index (thread and tile bits).
+struct CzaRec {
+  uint32_t sr;
+  uint32_t cmask[kMaxR];
+  uint32_t pad[2];
+};
+
+// Phase event definition for the coefficient kernel: w = u_a(prev) * u_c(next).
+struct EventRec {
+  int32_t prev_ref;   // coefficient ref of the run before (or INT32_MIN: none)
+  int32_t next_ref;   // coefficient ref of the run after (or INT32_MIN: none)
+  int32_t per_sample;
+  int32_t pad;
+};
+
+// Uniform address data of one layout.  Index of the amplitude held by thread
+// t in register slot jj:  T(t) ^ J(jj), with T(t) = XOR of thr[i] over the set
+// bits i of t and J(jj) = XOR of reg[j] over the set bits j of jj.  Three index
+// spaces: LDS element (XOR-swizzled), logical basis index (qubit q at bit q) and
+// memory index (only for load / store layouts).
+struct LayoutRec {
+  uint32_t lds_reg[kMaxR];
+  uint32_t lds_thr[kMaxThreadBits];
+  uint32_t log_reg[kMaxR];
+  uint32_t log_thr[kMaxThreadBits];
+  uint32_t mem_reg[kMaxR];
+  uint32_t mem_thr[kMaxThreadBits];
+  int32_t reg_qubit[kMaxR];
+  int32_t pad[1];
+};
+
+// XOR of per-bit contributions over the set bits of jj.
+inline uint32_t reg_index(const uint32_t* per_bit, int jj) {
+  uint32_t v = 0;
+  for (int j = 0; j < kMaxR; ++j)
+    if ((jj >> j) & 1) v ^= per_bit[j];
+  return v;
+}
 
 // CZ gates between qubits i and i+shift for every set bit i of mask.
 struct CzGroup {

@@ -8,6 +8,7 @@
 // GPU.  It is not a fallback: the device entry points never reach this code.
 #include <cmath>
 #include <complex>
+#include <climits>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -61,6 +62,7 @@ M2 dag(const M2& a) {
 struct CF {
   float re, im;
 };
+using cf = std::complex<float>;
 
 inline CF cmul(float ar, float ai, CF b) { return {ar * b.re - ai * b.im, ar * b.im + ai * b.re}; }
 
@@ -102,15 +104,76 @@ struct CpuExec {
     }
   }
 
-  void coef(const float* th, const float* xx, float* csh, float* cps) {
+  const float* ev_sh = nullptr;
+  const float* ev_ps = nullptr;
+
+  // RZ(a) RY(b) RZ(c) split: (cos b/2, sin b/2, e^{-ia/2}, e^{-ic/2}) and e^{-ia}.
+  struct Split {
+    double cb, sb;
+    cd u, v, z;
+  };
+  static Split split(const M2& V) {
+    Split o;
+    const double a0 = std::abs(V.m[0]), b0 = std::abs(V.m[2]);
+    const double nrm = std::sqrt(a0 * a0 + b0 * b0);
+    o.cb = a0 / nrm;
+    o.sb = b0 / nrm;
+    const cd A = a0 > 1e-300 ? V.m[0] / a0 : cd(1, 0);
+    const cd Bp = b0 > 1e-300 ? V.m[2] / b0 : cd(1, 0);
+    o.z = A * std::conj(Bp);
+    o.u = std::polar(1.0, 0.5 * std::arg(o.z));
+    o.v = A * std::conj(o.u);
+    return o;
+  }
+
+  void coef(const float* th, const float* xx, char* ws) {
     theta = th;
     x = xx;
+    float* csh = at<float>(ws, c.off_coef_sh);
+    float* cps = at<float>(ws, c.off_coef_ps);
+    float* esh = at<float>(ws, c.off_ev_sh);
+    float* eps = at<float>(ws, c.off_ev_ps);
     coef_sh = csh;
     coef_ps = cps;
-    for (size_t i = 0; i < c.coef_runs_sh.size(); ++i) put(csh + 8 * i, run_matrix(c.coef_runs_sh[i], 0));
+    ev_sh = esh;
+    ev_ps = eps;
+    auto put_run = [&](float* dst, int r, int b) {
+      const M2 U = run_matrix(r, b);
+      if (c.per_gate) {
+        put(dst, U);
+        return;
+      }
+      const Split z = split(U);
+      const float v[8] = {(float)z.cb, (float)z.sb, (float)z.u.real(), (float)z.u.imag(),
+                          (float)z.v.real(), (float)z.v.imag(), 0.f, 0.f};
+      std::memcpy(dst, v, sizeof(v));
+    };
+    for (size_t i = 0; i < c.coef_runs_sh.size(); ++i) put_run(csh + 8 * i, c.coef_runs_sh[i], 0);
     const int nps = (int)c.coef_runs_ps.size();
     for (int b = 0; b < c.B; ++b)
-      for (int i = 0; i < nps; ++i) put(cps + 8 * ((int64_t)b * nps + i), run_matrix(c.coef_runs_ps[i], b));
+      for (int i = 0; i < nps; ++i) put_run(cps + 8 * ((int64_t)b * nps + i), c.coef_runs_ps[i], b);
+    auto ev = [&](const EventRec& e, int b, float* out) {
+      cf w(1.f, 0.f);
+      if (e.prev_ref != INT32_MIN) {
+        const float* p = coef_row(e.prev_ref, b);
+        w = w * cf(p[2], p[3]);
+      }
+      if (e.next_ref != INT32_MIN) {
+        const float* p = coef_row(e.next_ref, b);
+        w = w * cf(p[4], p[5]);
+      }
+      out[0] = w.real();
+      out[1] = w.imag();
+    };
+    for (int i = 0; i < c.S.n_ev_shared; ++i) ev(c.S.events[i], 0, esh + 2 * i);
+    for (int b = 0; b < c.B; ++b)
+      for (int i = 0; i < c.S.n_ev_ps; ++i)
+        ev(c.S.events[c.S.n_ev_shared + i], b, eps + 2 * ((int64_t)b * c.S.n_ev_ps + i));
+  }
+
+  cf event_w(int ref, int sample) const {
+    const float* p = ref >= 0 ? ev_sh + 2 * ref : ev_ps + 2 * ((int64_t)sample * c.S.n_ev_ps + (-1 - ref));
+    return cf(p[0], p[1]);
   }
 
   const float* coef_row(int ref, int sample) const {
@@ -140,6 +203,20 @@ struct CpuExec {
           }
         std::fill(a.begin(), a.end(), CF{0, 0});
         std::fill(l.begin(), l.end(), CF{0, 0});
+        std::vector<cf> ph(active, cf(1.f, 0.f));   // pending per-thread phase
+        auto flush = [&]() {
+          for (int t = 0; t < active; ++t) {
+            for (int jj = 0; jj < NA; ++jj) {
+              cf v = cf(a[t * NA + jj].re, a[t * NA + jj].im) * ph[t];
+              a[t * NA + jj] = CF{v.real(), v.imag()};
+              if (L.bwd) {
+                cf w = cf(l[t * NA + jj].re, l[t * NA + jj].im) * ph[t];
+                l[t * NA + jj] = CF{w.real(), w.imag()};
+              }
+            }
+            ph[t] = cf(1.f, 0.f);
+          }
+        };
         auto tbase = [&](const uint32_t* tab, int t) {
           uint32_t v = 0;
           for (int i = 0; i < tb; ++i)
@@ -154,7 +231,7 @@ struct CpuExec {
               const LayoutRec& Ly = S.layouts[op.a];
               for (int t = 0; t < active; ++t)
                 for (int jj = 0; jj < NA; ++jj) {
-                  uint32_t xl = tlog | tbase(Ly.log_thr, t) | Ly.log_reg[jj];
+                  uint32_t xl = tlog | tbase(Ly.log_thr, t) | reg_index(Ly.log_reg, jj);
                   a[t * NA + jj] = (xl == 0) ? CF{1, 0} : CF{0, 0};
                 }
               break;
@@ -167,7 +244,7 @@ struct CpuExec {
               const uint32_t tm = op.c ? tout : tin;
               for (int t = 0; t < active; ++t)
                 for (int jj = 0; jj < NA; ++jj) {
-                  uint64_t idx = tm | tbase(Ly.mem_thr, t) | Ly.mem_reg[jj];
+                  uint64_t idx = tm | tbase(Ly.mem_thr, t) | reg_index(Ly.mem_reg, jj);
                   if (idx >= (uint64_t)c.amps) oob("load index");
                   const float* p = src + sl * stride + 2 * idx;
                   in_ws(p, 8, "load address");
@@ -176,13 +253,14 @@ struct CpuExec {
               break;
             }
             case OP_STORE: {
+              flush();
               const LayoutRec& Ly = S.layouts[op.a];
               const std::vector<CF>& v = L.bwd ? l : a;
               const uint32_t tm = op.c ? tout : tin;
               if (!L.dst) break;
               for (int t = 0; t < active; ++t)
                 for (int jj = 0; jj < NA; ++jj) {
-                  uint64_t idx = tm | tbase(Ly.mem_thr, t) | Ly.mem_reg[jj];
+                  uint64_t idx = tm | tbase(Ly.mem_thr, t) | reg_index(Ly.mem_reg, jj);
                   if (idx >= (uint64_t)c.amps) oob("store index");
                   float* p = L.dst + sl * L.dst_stride + 2 * idx;
                   in_ws(p, 8, "store address");
@@ -192,6 +270,7 @@ struct CpuExec {
               break;
             }
             case OP_PERM: {
+              flush();
               const LayoutRec& F = S.layouts[op.a];
               const LayoutRec& T = S.layouts[op.b];
               for (int which = 0; which < (L.bwd ? 2 : 1); ++which) {
@@ -199,69 +278,85 @@ struct CpuExec {
                 std::vector<char> seen(k_amps, 0);
                 for (int t = 0; t < active; ++t)
                   for (int jj = 0; jj < NA; ++jj) {
-                    uint32_t e = tbase(F.lds_thr, t) ^ F.lds_reg[jj];
+                    uint32_t e = tbase(F.lds_thr, t) ^ reg_index(F.lds_reg, jj);
                     if (e >= k_amps || seen[e]) throw std::runtime_error("LDS layout is not a bijection");
                     seen[e] = 1;
                     lds[e] = v[t * NA + jj];
                   }
                 for (int t = 0; t < active; ++t)
                   for (int jj = 0; jj < NA; ++jj) {
-                    uint32_t e = tbase(T.lds_thr, t) ^ T.lds_reg[jj];
+                    uint32_t e = tbase(T.lds_thr, t) ^ reg_index(T.lds_reg, jj);
                     if (e >= k_amps) oob("LDS read");
                     v[t * NA + jj] = lds[e];
                   }
               }
               break;
             }
-            case OP_U2:
-            case OP_U2ADJ: {
+            case OP_RY: {
               const float* u = coef_row(op.b, sample);
-              float u00r = u[0], u00i = u[1], u01r = u[2], u01i = u[3], u10r = u[4], u10i = u[5], u11r = u[6],
-                    u11i = u[7];
-              if (op.kind == OP_U2ADJ) {
-                float t01r = u01r, t01i = u01i;
-                u00i = -u00i;
-                u11i = -u11i;
-                u01r = u10r; u01i = -u10i;
-                u10r = t01r; u10i = -t01i;
-              }
+              const float cc = u[0], ss = L.bwd ? -u[1] : u[1];
               const int j = op.a;
-              for (int which = 0; which < (op.kind == OP_U2ADJ ? 2 : 1); ++which) {
+              for (int which = 0; which < (L.bwd ? 2 : 1); ++which) {
                 std::vector<CF>& v = which == 0 ? a : l;
                 for (int t = 0; t < active; ++t)
                   for (int jj = 0; jj < NA; ++jj) {
                     if ((jj >> j) & 1) continue;
                     CF x0 = v[t * NA + jj], x1 = v[t * NA + (jj | (1 << j))];
-                    CF p = cmul(u00r, u00i, x0), q = cmul(u01r, u01i, x1);
-                    CF r0{p.re + q.re, p.im + q.im};
-                    p = cmul(u10r, u10i, x0);
-                    q = cmul(u11r, u11i, x1);
-                    CF r1{p.re + q.re, p.im + q.im};
-                    v[t * NA + jj] = r0;
-                    v[t * NA + (jj | (1 << j))] = r1;
+                    v[t * NA + jj] = CF{cc * x0.re - ss * x1.re, cc * x0.im - ss * x1.im};
+                    v[t * NA + (jj | (1 << j))] = CF{ss * x0.re + cc * x1.re, ss * x0.im + cc * x1.im};
                   }
               }
               break;
             }
-            case OP_CZ: {
+            case OP_DIAGT: {
               const LayoutRec& Ly = S.layouts[op.a];
-              for (int t = 0; t < active; ++t)
-                for (int jj = 0; jj < NA; ++jj) {
-                  uint32_t xl = tlog | tbase(Ly.log_thr, t) | Ly.log_reg[jj];
-                  uint32_t par = 0;
-                  for (int gi = 0; gi < op.c; ++gi) {
-                    const CzGroup& g = S.czg[op.b + gi];
-                    par ^= xl & (xl >> g.shift) & g.mask;
-                  }
-                  if (__builtin_popcount(par) & 1) {
-                    CF& v = a[t * NA + jj];
-                    v = CF{-v.re, -v.im};
-                    if (L.bwd) {
-                      CF& w = l[t * NA + jj];
-                      w = CF{-w.re, -w.im};
-                    }
-                  }
+              for (int t = 0; t < active; ++t) {
+                const uint32_t xl = tlog | tbase(Ly.log_thr, t);
+                uint32_t par = 0;
+                for (int gi = 0; gi < op.c; ++gi) {
+                  const CzGroup& g = S.czg[op.b + gi];
+                  par ^= xl & (xl >> g.shift) & g.mask;
                 }
+                if (__builtin_popcount(par) & 1) ph[t] = -ph[t];
+                for (int ei = 0; ei < op.e; ++ei) {
+                  const PhaseEv& e = S.pev[op.d + ei];
+                  cf w = event_w(e.ref, sample);
+                  const bool bit = (xl >> e.q) & 1;
+                  if (bit != L.bwd) w = std::conj(w);
+                  ph[t] *= w;
+                }
+              }
+              break;
+            }
+            case OP_CZA: {
+              const CzaRec& cr = S.cza[op.a];
+              const LayoutRec& Ly = S.layouts[op.b];
+              for (int t = 0; t < active; ++t) {
+                const uint32_t xl = tlog | tbase(Ly.log_thr, t);
+                for (int jj = 0; jj < NA; ++jj) {
+                  int sgn = (cr.sr >> jj) & 1;
+                  for (int j = 0; j < R; ++j)
+                    if ((jj >> j) & 1) sgn ^= __builtin_popcount(xl & cr.cmask[j]) & 1;
+                  if (!sgn) continue;
+                  a[t * NA + jj] = CF{-a[t * NA + jj].re, -a[t * NA + jj].im};
+                  if (L.bwd) l[t * NA + jj] = CF{-l[t * NA + jj].re, -l[t * NA + jj].im};
+                }
+              }
+              break;
+            }
+            case OP_PHASEA: {
+              const PhaseEv& e = S.pev[op.b];
+              cf w = event_w(e.ref, sample);
+              if (L.bwd) w = std::conj(w);
+              for (int which = 0; which < (L.bwd ? 2 : 1); ++which) {
+                std::vector<CF>& v = which == 0 ? a : l;
+                for (int t = 0; t < active; ++t)
+                  for (int jj = 0; jj < NA; ++jj) {
+                    const cf f = ((jj >> op.a) & 1) ? std::conj(w) : w;
+                    cf y = cf(v[t * NA + jj].re, v[t * NA + jj].im) * f;
+                    v[t * NA + jj] = CF{y.real(), y.imag()};
+                  }
+              }
               break;
             }
             case OP_EXPECT: {
@@ -272,7 +367,7 @@ struct CpuExec {
                   float acc = 0;
                   for (int t = w * 64; t < std::min(active, (w + 1) * 64); ++t)
                     for (int jj = 0; jj < NA; ++jj) {
-                      uint32_t xl = tlog | tbase(Ly.log_thr, t) | Ly.log_reg[jj];
+                      uint32_t xl = tlog | tbase(Ly.log_thr, t) | reg_index(Ly.log_reg, jj);
                       CF v = a[t * NA + jj];
                       float p = v.re * v.re + v.im * v.im;
                       acc += (__builtin_popcount(xl & (uint32_t)c.C.obs[k].z_mask) & 1) ? -p : p;
@@ -288,7 +383,7 @@ struct CpuExec {
               const LayoutRec& Ly = S.layouts[op.a];
               for (int t = 0; t < active; ++t)
                 for (int jj = 0; jj < NA; ++jj) {
-                  uint32_t xl = tlog | tbase(Ly.log_thr, t) | Ly.log_reg[jj];
+                  uint32_t xl = tlog | tbase(Ly.log_thr, t) | reg_index(Ly.log_reg, jj);
                   float cc = 0;
                   for (int k = 0; k < K; ++k) {
                     float g = L.dE[(int64_t)sample * K + k];
@@ -304,6 +399,7 @@ struct CpuExec {
               for (int e = 0; e < op.a; ++e) {
                 const FuncEntry& fe = S.funcs[op.b + e];
                 const int j = fe.regbit;
+                float fw[3] = {0, 0, 0};
                 for (int w = 0; w < waves; ++w) {
                   float fx = 0, fy = 0, fz = 0;
                   for (int t = w * 64; t < std::min(active, (w + 1) * 64); ++t)
@@ -315,14 +411,17 @@ struct CpuExec {
                       fy += -(l0.re * p1.re + l0.im * p1.im) + (l1.re * p0.re + l1.im * p0.im);
                       fz += (l0.re * p0.im - l0.im * p0.re) - (l1.re * p1.im - l1.im * p1.re);
                     }
-                  const int64_t pf = (item * waves + w) * 3 * ns + 3 * fe.slot;
-                  if (fe.slot < 0 || fe.slot >= ns || pf + 3 > (int64_t)L.nb * tiles * waves * 3 * ns) oob("partF");
-                  float* dst = L.partF + pf;
-                  in_ws(dst, 12, "partF address");
-                  dst[0] = fx;
-                  dst[1] = fy;
-                  dst[2] = fz;
+                  fw[0] += fx;
+                  fw[1] += fy;
+                  fw[2] += fz;
                 }
+                const int64_t pf = item * 3 * ns + 3 * fe.slot;
+                if (fe.slot < 0 || fe.slot >= ns || pf + 3 > (int64_t)L.nb * tiles * 3 * ns) oob("partF");
+                float* dst = L.partF + pf;
+                in_ws(dst, 12, "partF address");
+                dst[0] = fw[0];
+                dst[1] = fw[1];
+                dst[2] = fw[2];
               }
               break;
             }
@@ -346,14 +445,16 @@ struct CpuExec {
 
   // grad_i = 1/2 Im<lambda| K_i P_i K_i^dag |psi> at the cut after the run,
   // K_i = product of the run's gates after gate i.
-  void run_grads(int r, int sample, double fx, double fy, double fz, float* Grow) const {
+  void run_grads(int r, int sample, double fx, double fy, double fz, float* Grow, bool zyz) const {
     const RunRec& rr = c.S.runs[r];
+    const cd z = zyz ? split(run_matrix(r, sample)).z : cd(1, 0);
     M2 Kc;
     Kc.m[0] = 1; Kc.m[1] = 0; Kc.m[2] = 0; Kc.m[3] = 1;
     for (int i = rr.gate_count - 1; i >= 0; --i) {
       const GateRec& g = c.S.gates[c.S.run_gates[rr.gate_begin + i]];
       M2 G = mul(mul(Kc, pauli(g.kind)), dag(Kc));
-      double gr = 0.5 * (G.m[2].real() * fx + G.m[2].imag() * fy + G.m[0].real() * fz);
+      const cd g10 = z * G.m[2];
+      double gr = 0.5 * (g10.real() * fx + g10.imag() * fy + G.m[0].real() * fz);
       Grow[g.out_idx] = (float)gr;
       Kc = mul(Kc, rot(g.kind, angle(g, sample)));
     }
@@ -367,9 +468,9 @@ struct CpuExec {
         const int ns = c.S.passes[rr.pass].n_slots;
         const float* base = partF + (int64_t)nb * c.partF_off[rr.pass];
         double f[3] = {0, 0, 0};
-        for (int it = 0; it < c.tiles * c.waves; ++it)
-          for (int P = 0; P < 3; ++P) f[P] += base[(((int64_t)s * c.tiles * c.waves) + it) * 3 * ns + 3 * rr.slot + P];
-        run_grads(r, sample0 + s, f[0], f[1], f[2], Gr + (int64_t)s * c.n_angle);
+        for (int it = 0; it < c.tiles; ++it)
+          for (int P = 0; P < 3; ++P) f[P] += base[(((int64_t)s * c.tiles) + it) * 3 * ns + 3 * rr.slot + P];
+        run_grads(r, sample0 + s, f[0], f[1], f[2], Gr + (int64_t)s * c.n_angle, true);
       }
   }
 
@@ -488,7 +589,7 @@ struct CpuExec {
         double f[3] = {0, 0, 0};
         for (int b = 0; b < c.pg_blocks; ++b)
           for (int P = 0; P < 3; ++P) f[P] += partF[(((int64_t)s * c.pg_chunk + slot) * c.pg_blocks + b) * 3 + P];
-        run_grads(r, sample0 + s, f[0], f[1], f[2], Gr + (int64_t)s * c.n_angle);
+        run_grads(r, sample0 + s, f[0], f[1], f[2], Gr + (int64_t)s * c.n_angle, false);
       }
   }
 };
@@ -553,9 +654,10 @@ int qfc_stats(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tunin
   PlanCore pc;
   st = build_plan_core(C, batch, T, &pc, &msg);
   if (st != QF_OK) { g_err = msg; return st; }
-  int64_t v[12] = {pc.P, pc.n_seg, pc.ckpt, pc.mb, pc.S.n_perm, pc.S.n_u2, pc.S.n_cz, (int64_t)pc.S.layouts.size(),
-                   (int64_t)pc.S.runs.size(), pc.S.k, pc.S.R, (int64_t)pc.ws_bytes};
-  for (int i = 0; i < n_out && i < 12; ++i) out[i] = v[i];
+  int64_t v[14] = {pc.P, pc.n_seg, pc.ckpt, pc.mb, pc.S.n_perm, pc.S.n_u2, pc.S.n_cz, (int64_t)pc.S.layouts.size(),
+                   (int64_t)pc.S.runs.size(), pc.S.k, pc.S.R, (int64_t)pc.ws_bytes, pc.S.n_diag_thread,
+                   pc.S.n_diag_amp};
+  for (int i = 0; i < n_out && i < 14; ++i) out[i] = v[i];
   return 0;
 }
 

@@ -21,6 +21,7 @@
 //   k_pg_*              one-kernel-per-gate baseline.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -41,8 +42,12 @@ struct KArgs {
   const CzGroup* czg;
   const FuncEntry* funcs;
   const PassRec* prec;
+  const PhaseEv* pev;
+  const CzaRec* cza;
   const float* coef_sh;
   const float* coef_ps;
+  const float* ev_sh;
+  const float* ev_ps;
   const float2* src0;
   const float2* src1;
   float2* dst;
@@ -52,15 +57,28 @@ struct KArgs {
   const uint32_t* zmask;
   long long s0, s1, sd;       // per-sample strides (float2 units)
   int n_ops;
-  int n_ps;
+  int n_ps;                   // per-sample run coefficient rows per sample
+  int n_evps;                 // per-sample phase event rows per sample
   int K;
   int sample0;
   int tiles_log2;
   int tb;                     // thread bits of the tile
   int do_expect;
+  int tile_elems;             // 2^k: LDS elements of the tile; wave partial sums follow
 };
 
-// Register-bit dispatch: expands STMT(J) for the compile-time bit J == j.
+// Plan tables are written before the launch and only read by it: load them
+// through the constant address space so that uniform reads become scalar loads.
+template <typename T>
+__device__ __forceinline__ T cld(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const __attribute__((address_space(4))) T*)(p);
+#else
+  return *p;
+#endif
+}
+
+// Register-bit dispatch: expands STMT with the compile-time bit J == j.
 #define QF_WITH_BIT(R, j, STMT)                      \
   switch (j) {                                       \
     case 0: { constexpr int J = 0; STMT; } break;    \
@@ -71,33 +89,55 @@ struct KArgs {
     default: break;                                  \
   }
 
-__device__ __forceinline__ uint32_t tbase(const uint32_t* __restrict__ tab, int t, int tb) {
+__device__ __forceinline__ uint32_t tbase(const uint32_t* tab, int t, int tb) {
   uint32_t v = 0;
 #pragma unroll
   for (int i = 0; i < kMaxThreadBits; ++i)
-    if (i < tb && ((t >> i) & 1)) v ^= tab[i];
+    if (i < tb && ((t >> i) & 1)) v ^= cld(tab + i);
   return v;
 }
 
-struct U2c {
-  float r00, i00, r01, i01, r10, i10, r11, i11;
+// Per-register-bit contributions of a layout, loaded once per op (uniform).
+template <int R>
+struct RegBits {
+  uint32_t v[R];
+  __device__ __forceinline__ void load(const uint32_t* p) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) v[j] = cld(p + j);
+  }
+  // XOR over the set bits of the compile-time register index jj
+  __device__ __forceinline__ uint32_t operator()(int jj) const {
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if ((jj >> j) & 1) r ^= v[j];
+    return r;
+  }
 };
 
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+// Real rotation [[c, -s], [s, c]] on the pairs along register bit J.
 template <int R, int J>
-__device__ __forceinline__ void apply_u2(float2 (&a)[1 << R], const U2c& u) {
+__device__ __forceinline__ void apply_ry(float2 (&a)[1 << R], float c, float s) {
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
     if (i & (1 << J)) continue;
-    constexpr int s = 1 << J;
-    const float2 x0 = a[i], x1 = a[i | s];
-    float2 y0, y1;
-    y0.x = u.r00 * x0.x - u.i00 * x0.y + u.r01 * x1.x - u.i01 * x1.y;
-    y0.y = u.r00 * x0.y + u.i00 * x0.x + u.r01 * x1.y + u.i01 * x1.x;
-    y1.x = u.r10 * x0.x - u.i10 * x0.y + u.r11 * x1.x - u.i11 * x1.y;
-    y1.y = u.r10 * x0.y + u.i10 * x0.x + u.r11 * x1.y + u.i11 * x1.x;
-    a[i] = y0;
-    a[i | s] = y1;
+    constexpr int m = 1 << J;
+    const float2 x0 = a[i], x1 = a[i | m];
+    a[i] = make_float2(fmaf(-s, x1.x, c * x0.x), fmaf(-s, x1.y, c * x0.y));
+    a[i | m] = make_float2(fmaf(s, x0.x, c * x1.x), fmaf(s, x0.y, c * x1.y));
   }
+}
+
+// Diagonal phase on register bit J: w where the bit is 0, conj(w) where it is 1.
+template <int R, int J>
+__device__ __forceinline__ void apply_phase_reg(float2 (&a)[1 << R], float2 w) {
+  const float2 wc = make_float2(w.x, -w.y);
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) a[i] = cmul(a[i], (i & (1 << J)) ? wc : w);
 }
 
 // Im<l|X_q|a>, Im<l|Y_q|a>, Im<l|Z_q|a> over the pairs along register bit J.
@@ -107,11 +147,27 @@ __device__ __forceinline__ void func3(const float2 (&a)[1 << R], const float2 (&
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
     if (i & (1 << J)) continue;
-    constexpr int s = 1 << J;
-    const float2 p0 = a[i], p1 = a[i | s], l0 = l[i], l1 = l[i | s];
-    fx += l0.x * p1.y - l0.y * p1.x + l1.x * p0.y - l1.y * p0.x;
-    fy += (l1.x * p0.x + l1.y * p0.y) - (l0.x * p1.x + l0.y * p1.y);
-    fz += (l0.x * p0.y - l0.y * p0.x) - (l1.x * p1.y - l1.y * p1.x);
+    constexpr int m = 1 << J;
+    const float2 p0 = a[i], p1 = a[i | m], l0 = l[i], l1 = l[i | m];
+    fx = fmaf(l0.x, p1.y, fx); fx = fmaf(-l0.y, p1.x, fx); fx = fmaf(l1.x, p0.y, fx); fx = fmaf(-l1.y, p0.x, fx);
+    fy = fmaf(l1.x, p0.x, fy); fy = fmaf(l1.y, p0.y, fy); fy = fmaf(-l0.x, p1.x, fy); fy = fmaf(-l0.y, p1.y, fy);
+    fz = fmaf(l0.x, p0.y, fz); fz = fmaf(-l0.y, p0.x, fz); fz = fmaf(-l1.x, p1.y, fz); fz = fmaf(l1.y, p1.x, fz);
+  }
+}
+
+template <int NA>
+__device__ __forceinline__ void scale_all(float2 (&a)[NA], float2 p) {
+#pragma unroll
+  for (int i = 0; i < NA; ++i) a[i] = cmul(a[i], p);
+}
+
+template <int NA>
+__device__ __forceinline__ void flip_signs(float2 (&a)[NA], uint32_t sign) {
+#pragma unroll
+  for (int jj = 0; jj < NA; ++jj) {
+    const uint32_t f = (sign << (31 - jj)) & 0x80000000u;
+    a[jj].x = __uint_as_float(__float_as_uint(a[jj].x) ^ f);
+    a[jj].y = __uint_as_float(__float_as_uint(a[jj].y) ^ f);
   }
 }
 
@@ -156,17 +212,18 @@ __device__ __forceinline__ float wave_reduce16(float (&v)[16], int lane) {
   return v[0];
 }
 
-__device__ __forceinline__ U2c load_u2(const KArgs& A, int ref, int sample, bool adjoint) {
-  const float* p = ref >= 0 ? A.coef_sh + 8 * (size_t)ref : A.coef_ps + 8 * ((size_t)sample * A.n_ps + (-1 - ref));
-  U2c u;
-  if (!adjoint) {
-    u.r00 = p[0]; u.i00 = p[1]; u.r01 = p[2]; u.i01 = p[3];
-    u.r10 = p[4]; u.i10 = p[5]; u.r11 = p[6]; u.i11 = p[7];
-  } else {   // u^dagger
-    u.r00 = p[0]; u.i00 = -p[1]; u.r01 = p[4]; u.i01 = -p[5];
-    u.r10 = p[2]; u.i10 = -p[3]; u.r11 = p[6]; u.i11 = -p[7];
-  }
-  return u;
+__device__ __forceinline__ const float* run_coef(const KArgs& A, int ref, int sample) {
+  return ref >= 0 ? A.coef_sh + 8 * (size_t)ref : A.coef_ps + 8 * ((size_t)sample * A.n_ps + (-1 - ref));
+}
+
+__device__ __forceinline__ float2 event_coef(const KArgs& A, int ref, int sample) {
+  const float* p = ref >= 0 ? A.ev_sh + 2 * (size_t)ref : A.ev_ps + 2 * ((size_t)sample * A.n_evps + (-1 - ref));
+  return make_float2(cld(p), cld(p + 1));
+}
+
+// For register patterns jj in [0, 32): the set of jj with bit j set.
+__device__ __forceinline__ uint32_t bit_pattern(int j) {
+  return j == 0 ? 0xAAAAAAAAu : j == 1 ? 0xCCCCCCCCu : j == 2 ? 0xF0F0F0F0u : j == 3 ? 0xFF00FF00u : 0xFFFF0000u;
 }
 
 template <int R, int NT, bool BWD>
@@ -183,14 +240,15 @@ __global__ __launch_bounds__(NT) void k_pass(const KArgs A) {
   const int sl = item >> A.tiles_log2;
   const int tile = item & ((1 << A.tiles_log2) - 1);
   const int sample = A.sample0 + sl;
-  const PassRec* __restrict__ P = A.prec;
+  const PassRec* P = A.prec;
 
   uint32_t tlog = 0, tin = 0, tout = 0;
-  for (int i = 0; i < P->n_nonlocal; ++i)
+  const int nnl = cld(&P->n_nonlocal);
+  for (int i = 0; i < nnl; ++i)
     if ((tile >> i) & 1) {
-      tlog |= 1u << P->nl_log[i];
-      tin |= 1u << P->nl_in[i];
-      tout |= 1u << P->nl_out[i];
+      tlog |= 1u << cld(&P->nl_log[i]);
+      tin |= 1u << cld(&P->nl_in[i]);
+      tout |= 1u << cld(&P->nl_out[i]);
     }
 
   float2 a[NA];
@@ -200,127 +258,180 @@ __global__ __launch_bounds__(NT) void k_pass(const KArgs A) {
     a[j] = make_float2(0.f, 0.f);
     l[j] = make_float2(0.f, 0.f);
   }
-  const int n_slots = P->n_slots;
+  const int n_slots = cld(&P->n_slots);
+  // pending per-thread phase of the diagonal gates on thread-held qubits; it
+  // multiplies psi (and, in the backward, lambda as well)
+  float2 ph = make_float2(1.f, 0.f);
+  bool pend = false;
 
+  // the next op record is fetched while the current one executes
+  Op next = cld(A.ops);
   for (int oi = 0; oi < A.n_ops; ++oi) {
-    const Op op = A.ops[oi];
+    const Op op = next;
+    if (oi + 1 < A.n_ops) next = cld(A.ops + oi + 1);
     switch (op.kind) {
       case OP_INIT0: {
-        const LayoutRec* __restrict__ L = A.layouts + op.a;
+        const LayoutRec* L = A.layouts + op.a;
         const uint32_t base = tlog | tbase(L->log_thr, t, tb);
+        RegBits<R> rb;
+        rb.load(L->log_reg);
 #pragma unroll
         for (int jj = 0; jj < NA; ++jj)
-          a[jj] = make_float2((active && (base | L->log_reg[jj]) == 0u) ? 1.f : 0.f, 0.f);
+          a[jj] = make_float2((active && (base | rb(jj)) == 0u) ? 1.f : 0.f, 0.f);
         break;
       }
       case OP_LOAD: {
-        const LayoutRec* __restrict__ L = A.layouts + op.a;
+        const LayoutRec* L = A.layouts + op.a;
         const uint32_t base = (op.c ? tout : tin) | tbase(L->mem_thr, t, tb);
+        RegBits<R> rb;
+        rb.load(L->mem_reg);
         if (active) {
           if (op.b == 0) {
-            const float2* __restrict__ src = A.src0 + (long long)sl * A.s0;
+            const float2* src = A.src0 + (long long)sl * A.s0;
 #pragma unroll
-            for (int jj = 0; jj < NA; ++jj) a[jj] = src[base | L->mem_reg[jj]];
+            for (int jj = 0; jj < NA; ++jj) a[jj] = src[base | rb(jj)];
           } else if constexpr (BWD) {
-            const float2* __restrict__ src = A.src1 + (long long)sl * A.s1;
+            const float2* src = A.src1 + (long long)sl * A.s1;
 #pragma unroll
-            for (int jj = 0; jj < NA; ++jj) l[jj] = src[base | L->mem_reg[jj]];
+            for (int jj = 0; jj < NA; ++jj) l[jj] = src[base | rb(jj)];
           }
         }
         break;
       }
       case OP_STORE: {
-        const LayoutRec* __restrict__ L = A.layouts + op.a;
+        if (pend) {
+          scale_all<NA>(a, ph);
+          if constexpr (BWD) scale_all<NA>(l, ph);
+          ph = make_float2(1.f, 0.f);
+          pend = false;
+        }
+        const LayoutRec* L = A.layouts + op.a;
         const uint32_t base = (op.c ? tout : tin) | tbase(L->mem_thr, t, tb);
+        RegBits<R> rb;
+        rb.load(L->mem_reg);
         if (active && A.dst) {
-          float2* __restrict__ dst = A.dst + (long long)sl * A.sd;
+          float2* dst = A.dst + (long long)sl * A.sd;
           if constexpr (BWD) {
 #pragma unroll
-            for (int jj = 0; jj < NA; ++jj) dst[base | L->mem_reg[jj]] = l[jj];
+            for (int jj = 0; jj < NA; ++jj) dst[base | rb(jj)] = l[jj];
           } else {
 #pragma unroll
-            for (int jj = 0; jj < NA; ++jj) dst[base | L->mem_reg[jj]] = a[jj];
+            for (int jj = 0; jj < NA; ++jj) dst[base | rb(jj)] = a[jj];
           }
         }
         break;
       }
       case OP_PERM: {
-        const LayoutRec* __restrict__ F = A.layouts + op.a;
-        const LayoutRec* __restrict__ T = A.layouts + op.b;
+        if (pend) {
+          scale_all<NA>(a, ph);
+          if constexpr (BWD) scale_all<NA>(l, ph);
+          ph = make_float2(1.f, 0.f);
+          pend = false;
+        }
+        const LayoutRec* F = A.layouts + op.a;
+        const LayoutRec* T = A.layouts + op.b;
         const uint32_t bf = tbase(F->lds_thr, t, tb);
         const uint32_t bt = tbase(T->lds_thr, t, tb);
+        RegBits<R> rf, rt;
+        rf.load(F->lds_reg);
+        rt.load(T->lds_reg);
         if (active) {
 #pragma unroll
-          for (int jj = 0; jj < NA; ++jj) lds[bf ^ F->lds_reg[jj]] = a[jj];
+          for (int jj = 0; jj < NA; ++jj) lds[bf ^ rf(jj)] = a[jj];
         }
         __syncthreads();
         if (active) {
 #pragma unroll
-          for (int jj = 0; jj < NA; ++jj) a[jj] = lds[bt ^ T->lds_reg[jj]];
+          for (int jj = 0; jj < NA; ++jj) a[jj] = lds[bt ^ rt(jj)];
         }
         __syncthreads();
         if constexpr (BWD) {
           if (active) {
 #pragma unroll
-            for (int jj = 0; jj < NA; ++jj) lds[bf ^ F->lds_reg[jj]] = l[jj];
+            for (int jj = 0; jj < NA; ++jj) lds[bf ^ rf(jj)] = l[jj];
           }
           __syncthreads();
           if (active) {
 #pragma unroll
-            for (int jj = 0; jj < NA; ++jj) l[jj] = lds[bt ^ T->lds_reg[jj]];
+            for (int jj = 0; jj < NA; ++jj) l[jj] = lds[bt ^ rt(jj)];
           }
           __syncthreads();
         }
         break;
       }
-      case OP_U2: {
-        const U2c u = load_u2(A, op.b, sample, false);
-        QF_WITH_BIT(R, op.a, (apply_u2<R, J>(a, u)));
-        break;
-      }
-      case OP_U2ADJ: {
+      case OP_RY: {
+        const float* cp = run_coef(A, op.b, sample);
+        const float c = cld(cp);
+        const float s = BWD ? -cld(cp + 1) : cld(cp + 1);
         if constexpr (BWD) {
-          const U2c u = load_u2(A, op.b, sample, true);
-          QF_WITH_BIT(R, op.a, (apply_u2<R, J>(a, u), apply_u2<R, J>(l, u)));
+          QF_WITH_BIT(R, op.a, (apply_ry<R, J>(a, c, s), apply_ry<R, J>(l, c, s)));
+        } else {
+          QF_WITH_BIT(R, op.a, (apply_ry<R, J>(a, c, s)));
         }
         break;
       }
-      case OP_CZ: {
-        const LayoutRec* __restrict__ L = A.layouts + op.a;
-        const uint32_t base = tlog | tbase(L->log_thr, t, tb);
-        const CzGroup* __restrict__ g = A.czg + op.b;
-        const int ng = op.c;
+      case OP_DIAGT: {
+        const LayoutRec* L = A.layouts + op.a;
+        const uint32_t x = tlog | tbase(L->log_thr, t, tb);
+        uint32_t par = 0;
+        for (int i = 0; i < op.c; ++i) {
+          const CzGroup g = cld(A.czg + op.b + i);
+          par ^= x & (x >> g.shift) & g.mask;
+        }
+        const uint32_t f = (uint32_t)(__popc(par) & 1) << 31;
+        ph.x = __uint_as_float(__float_as_uint(ph.x) ^ f);
+        ph.y = __uint_as_float(__float_as_uint(ph.y) ^ f);
+        for (int i = 0; i < op.e; ++i) {
+          const PhaseEv e = cld(A.pev + op.d + i);
+          float2 w = event_coef(A, e.ref, sample);
+          const bool conj = (((x >> e.q) & 1u) != 0u) != BWD;
+          if (conj) w.y = -w.y;
+          ph = cmul(ph, w);
+        }
+        pend = true;
+        break;
+      }
+      case OP_CZA: {
+        const CzaRec* C = A.cza + op.a;
+        const LayoutRec* L = A.layouts + op.b;
+        const uint32_t x = tlog | tbase(L->log_thr, t, tb);
+        uint32_t sign = cld(&C->sr);
 #pragma unroll
-        for (int jj = 0; jj < NA; ++jj) {
-          const uint32_t x = base | L->log_reg[jj];
-          uint32_t par = 0;
-          for (int i = 0; i < ng; ++i) par ^= x & (x >> g[i].shift) & g[i].mask;
-          const uint32_t flip = (uint32_t)(__popc(par) & 1) << 31;
-          a[jj].x = __uint_as_float(__float_as_uint(a[jj].x) ^ flip);
-          a[jj].y = __uint_as_float(__float_as_uint(a[jj].y) ^ flip);
-          if constexpr (BWD) {
-            l[jj].x = __uint_as_float(__float_as_uint(l[jj].x) ^ flip);
-            l[jj].y = __uint_as_float(__float_as_uint(l[jj].y) ^ flip);
-          }
+        for (int j = 0; j < R; ++j)
+          if (__popc(x & cld(&C->cmask[j])) & 1) sign ^= bit_pattern(j);
+        flip_signs<NA>(a, sign);
+        if constexpr (BWD) flip_signs<NA>(l, sign);
+        break;
+      }
+      case OP_PHASEA: {
+        const PhaseEv e = cld(A.pev + op.b);
+        float2 w = event_coef(A, e.ref, sample);
+        if (BWD) w.y = -w.y;
+        if constexpr (BWD) {
+          QF_WITH_BIT(R, op.a, (apply_phase_reg<R, J>(a, w), apply_phase_reg<R, J>(l, w)));
+        } else {
+          QF_WITH_BIT(R, op.a, (apply_phase_reg<R, J>(a, w)));
         }
         break;
       }
       case OP_EXPECT: {
         if constexpr (!BWD) {
           if (!A.do_expect) break;
-          const LayoutRec* __restrict__ L = A.layouts + op.a;
+          const LayoutRec* L = A.layouts + op.a;
           const uint32_t base = tlog | tbase(L->log_thr, t, tb);
+          RegBits<R> rb;
+          rb.load(L->log_reg);
           for (int k0 = 0; k0 < A.K; k0 += 16) {
             float v[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) v[k] = 0.f;
 #pragma unroll
             for (int jj = 0; jj < NA; ++jj) {
-              const uint32_t x = base | L->log_reg[jj];
-              const float p = a[jj].x * a[jj].x + a[jj].y * a[jj].y;
+              const uint32_t x = base | rb(jj);
+              const float p = fmaf(a[jj].x, a[jj].x, a[jj].y * a[jj].y);
 #pragma unroll
               for (int k = 0; k < 16; ++k)
-                if (k0 + k < A.K) v[k] += (__popc(x & A.zmask[k0 + k]) & 1) ? -p : p;
+                if (k0 + k < A.K) v[k] += (__popc(x & cld(A.zmask + k0 + k)) & 1) ? -p : p;
             }
             const float s = wave_reduce16(v, lane);
             const int idx = (lane >> 2) & 15;
@@ -332,43 +443,73 @@ __global__ __launch_bounds__(NT) void k_pass(const KArgs A) {
       }
       case OP_SEED: {
         if constexpr (BWD) {
-          const LayoutRec* __restrict__ L = A.layouts + op.a;
+          const LayoutRec* L = A.layouts + op.a;
           const uint32_t base = tlog | tbase(L->log_thr, t, tb);
-          const float* __restrict__ g = A.dE + (size_t)sample * A.K;
+          RegBits<R> rb;
+          rb.load(L->log_reg);
+          const float* g = A.dE + (size_t)sample * A.K;
+          // lambda = 2 c(x) psi, c(x) = sum_k g_k (-1)^{|x & z_k|}
+          float c[NA];
 #pragma unroll
-          for (int jj = 0; jj < NA; ++jj) {
-            const uint32_t x = base | L->log_reg[jj];
-            float c = 0.f;
-            for (int k = 0; k < A.K; ++k) c += (__popc(x & A.zmask[k]) & 1) ? -g[k] : g[k];
-            l[jj] = make_float2(2.f * c * a[jj].x, 2.f * c * a[jj].y);
+          for (int jj = 0; jj < NA; ++jj) c[jj] = 0.f;
+#pragma unroll 1
+          for (int k = 0; k < A.K; ++k) {
+            const float gk = cld(g + k);
+            const uint32_t zk = cld(A.zmask + k);
+#pragma unroll
+            for (int jj = 0; jj < NA; ++jj) c[jj] += (__popc((base | rb(jj)) & zk) & 1) ? -gk : gk;
           }
+#pragma unroll
+          for (int jj = 0; jj < NA; ++jj) l[jj] = make_float2(2.f * c[jj] * a[jj].x, 2.f * c[jj] * a[jj].y);
         }
         break;
       }
       case OP_FUNC: {
         if constexpr (BWD) {
-          const FuncEntry* __restrict__ fe = A.funcs + op.b;
+          const FuncEntry* fe = A.funcs + op.b;
           const int m = op.a;
           float v[16];
 #pragma unroll
           for (int i = 0; i < 16; ++i) v[i] = 0.f;
+#pragma unroll 1
+          for (int e = 0; e < m; ++e) {
+            float fx = 0.f, fy = 0.f, fz = 0.f;
+            const int rb = cld(&fe[e].regbit);
+            QF_WITH_BIT(R, rb, (func3<R, J>(a, l, fx, fy, fz)));
+            // place the three sums of entry e (static register indices)
 #pragma unroll
-          for (int e = 0; e < R; ++e) {
-            if (e < m) {
-              QF_WITH_BIT(R, fe[e].regbit, (func3<R, J>(a, l, v[3 * e], v[3 * e + 1], v[3 * e + 2])));
-            }
+            for (int q = 0; q < R; ++q)
+              if (q == e) {
+                v[3 * q] = fx;
+                v[3 * q + 1] = fy;
+                v[3 * q + 2] = fz;
+              }
           }
           const float s = wave_reduce16(v, lane);
           const int idx = (lane >> 2) & 15;
           if ((lane & 3) == 0 && idx < 3 * m) {
             const int e = idx / 3, pq = idx - 3 * e;
-            A.partF[((size_t)item * WAVES + wave) * 3 * n_slots + 3 * fe[e].slot + pq] = s;
+            float* part = reinterpret_cast<float*>(lds + A.tile_elems);
+            part[wave * 3 * n_slots + 3 * fe[e].slot + pq] = s;
           }
         }
         break;
       }
       default:
         break;
+    }
+  }
+  if constexpr (BWD) {
+    // one partial sum per tile and functional: add the waves' sums
+    if (n_slots > 0) {
+      __syncthreads();
+      const float* part = reinterpret_cast<const float*>(lds + A.tile_elems);
+      for (int i = t; i < 3 * n_slots; i += NT) {
+        float acc = 0.f;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) acc += part[w * 3 * n_slots + i];
+        A.partF[(size_t)item * 3 * n_slots + i] = acc;
+      }
     }
   }
 }
@@ -435,6 +576,7 @@ __device__ inline D2 d2_dag(const D2& a) {
 }
 
 struct Tabs {
+  const EventRec* events;
   const RunRec* runs;
   const int32_t* run_gates;
   const GateRec* gates;
@@ -448,14 +590,57 @@ struct Tabs {
   const int32_t* th_refs;
   const int32_t* in_ref_begin;
   const int32_t* in_refs;
+  const int32_t* pass_run_begin;
+  const int32_t* pass_runs;
 };
 
 __device__ inline double gate_angle(const GateRec& g, const float* theta, const float* x, int F, int sample) {
   return g.theta_idx >= 0 ? (double)theta[g.theta_idx] : (double)x[(size_t)sample * F + g.input_idx];
 }
 
+// RZ(a) RY(b) RZ(c) split of an SU(2) matrix V (V00 = e^{-i(a+c)/2} cos(b/2),
+// V10 = e^{i(a-c)/2} sin(b/2)).  Returns cos(b/2), sin(b/2), u = e^{-ia/2},
+// v = e^{-ic/2} and z = u^2 = e^{-ia}.
+struct ZYZ {
+  double cb, sb, ur, ui, vr, vi, zr, zi;
+};
+
+__device__ inline ZYZ zyz_split(const D2& V) {
+  ZYZ o;
+  const double a0 = sqrt(V.r[0] * V.r[0] + V.i[0] * V.i[0]);
+  const double b0 = sqrt(V.r[2] * V.r[2] + V.i[2] * V.i[2]);
+  const double nrm = sqrt(a0 * a0 + b0 * b0);
+  o.cb = a0 / nrm;
+  o.sb = b0 / nrm;
+  double Ar = 1, Ai = 0, Br = 1, Bi = 0;
+  if (a0 > 1e-300) { Ar = V.r[0] / a0; Ai = V.i[0] / a0; }
+  if (b0 > 1e-300) { Br = V.r[2] / b0; Bi = V.i[2] / b0; }
+  o.zr = Ar * Br + Ai * Bi;        // A conj(B)
+  o.zi = Ai * Br - Ar * Bi;
+  const double th = atan2(o.zi, o.zr);
+  double s, c;
+  sincos(0.5 * th, &s, &c);
+  o.ur = c;
+  o.ui = s;
+  o.vr = Ar * c + Ai * s;          // A conj(u)
+  o.vi = Ai * c - Ar * s;
+  return o;
+}
+
+__device__ inline D2 run_matrix(const Tabs& T, const RunRec& rr, const float* theta, const float* x, int F,
+                                int sample) {
+  D2 U = d2_eye();
+  for (int i = 0; i < rr.gate_count; ++i) {
+    const GateRec g = T.gates[T.run_gates[rr.gate_begin + i]];
+    U = d2_mul(d2_rot(g.kind, gate_angle(g, theta, x, F, sample)), U);
+  }
+  return U;
+}
+
+// Run coefficients.  zyz = 1: [cos(b/2), sin(b/2), u, v] of the RZ RY RZ split;
+// zyz = 0: the 2x2 matrix row-major (one-gate runs of the per-gate baseline).
 __global__ void k_coef(Tabs T, const float* theta, const float* x, int F, int n_sh, int n_ps, int B, float* csh,
-                       float* cps) {
+                       float* cps, int zyz) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long total = n_sh + (long long)n_ps * B;
   if (idx >= total) return;
@@ -472,48 +657,106 @@ __global__ void k_coef(Tabs T, const float* theta, const float* x, int F, int n_
     r = T.coef_runs_ps[i];
     out = cps + 8 * j;
   }
-  const RunRec rr = T.runs[r];
-  D2 U = d2_eye();
-  for (int i = 0; i < rr.gate_count; ++i) {
-    const GateRec g = T.gates[T.run_gates[rr.gate_begin + i]];
-    U = d2_mul(d2_rot(g.kind, gate_angle(g, theta, x, F, sample)), U);
-  }
-  for (int i = 0; i < 4; ++i) {
-    out[2 * i] = (float)U.r[i];
-    out[2 * i + 1] = (float)U.i[i];
+  const D2 U = run_matrix(T, T.runs[r], theta, x, F, sample);
+  if (zyz) {
+    const ZYZ z = zyz_split(U);
+    out[0] = (float)z.cb; out[1] = (float)z.sb;
+    out[2] = (float)z.ur; out[3] = (float)z.ui;
+    out[4] = (float)z.vr; out[5] = (float)z.vi;
+    out[6] = 0.f; out[7] = 0.f;
+  } else {
+    for (int i = 0; i < 4; ++i) {
+      out[2 * i] = (float)U.r[i];
+      out[2 * i + 1] = (float)U.i[i];
+    }
   }
 }
 
+// Phase event coefficients w = u(prev run) * v(next run).
+__global__ void k_event_coef(Tabs T, int n_ev_sh, int n_ev_ps, int B, int n_ps, const float* csh, const float* cps,
+                             float* esh, float* eps) {
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = n_ev_sh + (long long)n_ev_ps * B;
+  if (idx >= total) return;
+  int sample = 0;
+  EventRec e;
+  float* out;
+  if (idx < n_ev_sh) {
+    e = T.events[idx];
+    out = esh + 2 * idx;
+  } else {
+    const long long j = idx - n_ev_sh;
+    sample = (int)(j / n_ev_ps);
+    const int i = (int)(j - (long long)sample * n_ev_ps);
+    e = T.events[n_ev_sh + i];
+    out = eps + 2 * j;
+  }
+  auto row = [&](int ref) {
+    return ref >= 0 ? csh + 8 * (long long)ref : cps + 8 * ((long long)sample * n_ps + (-1 - ref));
+  };
+  float wr = 1.f, wi = 0.f;
+  if (e.prev_ref != INT32_MIN) {
+    const float* p = row(e.prev_ref);
+    const float ur = p[2], ui = p[3];
+    const float tr = wr * ur - wi * ui, ti = wr * ui + wi * ur;
+    wr = tr; wi = ti;
+  }
+  if (e.next_ref != INT32_MIN) {
+    const float* p = row(e.next_ref);
+    const float vr = p[4], vi = p[5];
+    const float tr = wr * vr - wi * vi, ti = wr * vi + wi * vr;
+    wr = tr; wi = ti;
+  }
+  out[0] = wr;
+  out[1] = wi;
+}
+
+// Gradients of the gates of run r from the functionals F = Im<lambda|P_q|psi>
+// (P = X, Y, Z) taken at the cut right after the run's RY (zyz = 1) or right
+// after the whole run (zyz = 0).  dL/dtheta_g = 1/2 Im<lambda|G|psi>, with G the
+// generator of gate g carried to the cut: G = K P_g K^dagger (K = gates of the
+// run after g), conjugated by RZ(a)^dagger for the zyz cut.  Writing
+// G = n_x X + n_y Y + n_z Z gives dL/dtheta_g = 1/2 (n . F).
 __device__ inline void run_grads(const Tabs& T, int r, const float* theta, const float* x, int F, int sample,
-                                 double fx, double fy, double fz, float* Grow) {
+                                 double fx, double fy, double fz, float* Grow, int zyz) {
   const RunRec rr = T.runs[r];
+  double zr = 1, zi = 0;
+  if (zyz) {
+    const ZYZ z = zyz_split(run_matrix(T, rr, theta, x, F, sample));
+    zr = z.zr;
+    zi = z.zi;
+  }
   D2 K = d2_eye();
   for (int i = rr.gate_count - 1; i >= 0; --i) {
     const GateRec g = T.gates[T.run_gates[rr.gate_begin + i]];
     const D2 G = d2_mul(d2_mul(K, d2_pauli(g.kind)), d2_dag(K));
-    Grow[g.out_idx] = (float)(0.5 * (G.r[2] * fx + G.i[2] * fy + G.r[0] * fz));
+    const double gr = zr * G.r[2] - zi * G.i[2], gi = zr * G.i[2] + zi * G.r[2];
+    Grow[g.out_idx] = (float)(0.5 * (gr * fx + gi * fy + G.r[0] * fz));
     K = d2_mul(K, d2_rot(g.kind, gate_angle(g, theta, x, F, sample)));
   }
 }
 
-__global__ void k_assemble(Tabs T, int seg, int nb, int sample0, int tiles_waves, int n_angle, const float* theta,
-                           const float* x, int F, const float* partF, float* Gr) {
-  const int r0 = T.seg_run_begin[seg], nr = T.seg_run_begin[seg + 1] - r0;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)nr * nb) return;
-  const int s = (int)(idx / nr), i = (int)(idx - (long long)s * nr);
-  const int r = T.seg_runs[r0 + i];
-  const RunRec rr = T.runs[r];
-  const int ns = T.passes[rr.pass].n_slots;
-  const float* base = partF + (long long)nb * T.partF_off[rr.pass] + (long long)s * tiles_waves * 3 * ns + 3 * rr.slot;
-  double f0 = 0, f1 = 0, f2 = 0;
-  for (int it = 0; it < tiles_waves; ++it) {
-    const float* p = base + (long long)it * 3 * ns;
-    f0 += p[0];
-    f1 += p[1];
-    f2 += p[2];
+// One block per (sample, pass of the segment): sum the pass's per-tile
+// functional partials (coalesced over the slots), then one thread per run turns
+// the three sums into the run's per-gate gradients.
+__global__ __launch_bounds__(256) void k_assemble(Tabs T, int p0, int np, int nb, int sample0, int tiles,
+                                                  int n_angle, const float* theta, const float* x, int F,
+                                                  const float* partF, float* Gr) {
+  extern __shared__ double fsum[];
+  const int s = blockIdx.x / np, p = p0 + (int)(blockIdx.x - s * np);
+  const int ns = T.passes[p].n_slots;
+  if (ns == 0) return;
+  const float* base = partF + (long long)nb * T.partF_off[p] + (long long)s * tiles * 3 * ns;
+  for (int v = threadIdx.x; v < 3 * ns; v += blockDim.x) {
+    double acc = 0;
+    for (int tile = 0; tile < tiles; ++tile) acc += base[(long long)tile * 3 * ns + v];
+    fsum[v] = acc;
   }
-  run_grads(T, r, theta, x, F, sample0 + s, f0, f1, f2, Gr + (long long)s * n_angle);
+  __syncthreads();
+  const int rb = T.pass_run_begin[p];
+  for (int i = threadIdx.x; i < ns; i += blockDim.x)
+    run_grads(T, T.pass_runs[rb + i], theta, x, F, sample0 + s, fsum[3 * i], fsum[3 * i + 1], fsum[3 * i + 2],
+              Gr + (long long)s * n_angle, 1);
 }
 
 __global__ void k_reduce_grads(Tabs T, int nb, int sample0, int n_angle, int P, int F, const float* Gr,
@@ -679,7 +922,7 @@ __global__ void k_pg_assemble(Tabs T, int r0, int cnt, int nb, int chunk, int bl
   double f[3] = {0, 0, 0};
   for (int b = 0; b < blocks; ++b)
     for (int P = 0; P < 3; ++P) f[P] += partF[(((long long)s * chunk + slot) * blocks + b) * 3 + P];
-  run_grads(T, r, theta, x, F, sample0 + s, f[0], f[1], f[2], Gr + (long long)s * n_angle);
+  run_grads(T, r, theta, x, F, sample0 + s, f[0], f[1], f[2], Gr + (long long)s * n_angle, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -694,6 +937,8 @@ struct DevPlan {
   const FuncEntry* funcs = nullptr;
   const PassRec* passes = nullptr;
   const uint32_t* zmask = nullptr;
+  const PhaseEv* pev = nullptr;
+  const CzaRec* cza = nullptr;
   Tabs tabs{};
 };
 
@@ -728,6 +973,11 @@ static qf_status upload_plan(const PlanCore& c, DevPlan* d, std::string* msg) {
   push_table(blob, o, c.th_refs);        // 15
   push_table(blob, o, c.in_ref_begin);   // 16
   push_table(blob, o, c.in_refs);        // 17
+  push_table(blob, o, c.S.pev);          // 18
+  push_table(blob, o, c.S.cza);          // 19
+  push_table(blob, o, c.S.events);       // 20
+  push_table(blob, o, c.S.pass_run_begin);  // 21
+  push_table(blob, o, c.S.pass_runs);    // 22
   d->bytes = blob.size();
   if (hipMalloc(&d->blob, d->bytes) != hipSuccess) {
     if (msg) *msg = "hipMalloc of plan tables failed";
@@ -758,6 +1008,11 @@ static qf_status upload_plan(const PlanCore& c, DevPlan* d, std::string* msg) {
   t.th_refs = (const int32_t*)(b + o[15]);
   t.in_ref_begin = (const int32_t*)(b + o[16]);
   t.in_refs = (const int32_t*)(b + o[17]);
+  d->pev = (const PhaseEv*)(b + o[18]);
+  d->cza = (const CzaRec*)(b + o[19]);
+  t.events = (const EventRec*)(b + o[20]);
+  t.pass_run_begin = (const int32_t*)(b + o[21]);
+  t.pass_runs = (const int32_t*)(b + o[22]);
   return QF_OK;
 }
 
@@ -774,6 +1029,10 @@ static PassFn select_pass(int R, int NT, bool bwd) {
     if (NT == 128) return bwd ? pass_fn<5, 128, true>() : pass_fn<5, 128, false>();
     if (NT == 256) return bwd ? pass_fn<5, 256, true>() : pass_fn<5, 256, false>();
     return nullptr;
+  }
+  if (R == 4) {
+    if (NT == 128) return bwd ? pass_fn<4, 128, true>() : pass_fn<4, 128, false>();
+    if (NT == 256) return bwd ? pass_fn<4, 256, true>() : pass_fn<4, 256, false>();
   }
   if (NT != 64) return nullptr;
   switch (R) {
@@ -841,15 +1100,31 @@ struct GpuExec {
   qf_status status() const { return err; }
   static unsigned blocks_for(long long n, int t = 256) { return (unsigned)std::max<long long>(1, (n + t - 1) / t); }
 
-  void coef(const float* th, const float* xx, float* cs, float* cp) {
-    theta = th; x = xx; csh = cs; cps = cp;
+  const float* esh = nullptr;
+  const float* eps = nullptr;
+  void coef(const float* th, const float* xx, char* ws) {
+    theta = th; x = xx;
+    float* cs = at<float>(ws, c.off_coef_sh);
+    float* cp = at<float>(ws, c.off_coef_ps);
+    float* es = at<float>(ws, c.off_ev_sh);
+    float* ep = at<float>(ws, c.off_ev_ps);
+    csh = cs; cps = cp; esh = es; eps = ep;
     const long long total = c.S.n_coef_shared + (long long)c.S.n_coef_ps * c.B;
-    if (total == 0) return;
-    pb();
-    hipLaunchKernelGGL(k_coef, dim3(blocks_for(total)), dim3(256), 0, st, d.tabs, th, xx, c.C.F, c.S.n_coef_shared,
-                       c.S.n_coef_ps, c.B, cs, cp);
-    pe(2);
-    check("k_coef");
+    if (total > 0) {
+      pb();
+      hipLaunchKernelGGL(k_coef, dim3(blocks_for(total)), dim3(256), 0, st, d.tabs, th, xx, c.C.F, c.S.n_coef_shared,
+                         c.S.n_coef_ps, c.B, cs, cp, c.per_gate ? 0 : 1);
+      pe(2);
+      check("k_coef");
+    }
+    const long long ne = c.S.n_ev_shared + (long long)c.S.n_ev_ps * c.B;
+    if (ne > 0) {
+      pb();
+      hipLaunchKernelGGL(k_event_coef, dim3(blocks_for(ne)), dim3(256), 0, st, d.tabs, c.S.n_ev_shared,
+                         c.S.n_ev_ps, c.B, c.S.n_coef_ps, cs, cp, es, ep);
+      pe(2);
+      check("k_event_coef");
+    }
   }
 
   void pass(const PassLaunch& L) {
@@ -862,9 +1137,14 @@ struct GpuExec {
     A.czg = d.czg;
     A.funcs = d.funcs;
     A.prec = d.passes + L.pass;
+    A.pev = d.pev;
+    A.cza = d.cza;
     A.coef_sh = csh;
     A.coef_ps = cps;
+    A.ev_sh = esh;
+    A.ev_ps = eps;
     A.n_ps = S.n_coef_ps;
+    A.n_evps = S.n_ev_ps;
     A.src0 = (const float2*)L.src0;
     A.s0 = L.src0_stride / 2;
     A.src1 = (const float2*)L.src1;
@@ -885,7 +1165,8 @@ struct GpuExec {
       if (err == QF_OK) { err = QF_ERR_UNSUPPORTED; msg = "no pass kernel for this tile shape"; }
       return;
     }
-    const size_t shmem = sizeof(float2) << S.k;
+    A.tile_elems = 1 << S.k;
+    const size_t shmem = (sizeof(float2) << S.k) + (L.bwd ? sizeof(float) * 3 * S.max_slots * S.NT / 64 : 0);
     pb();
     hipLaunchKernelGGL(fn, dim3((unsigned)((long long)L.nb << S.tiles_log2)), dim3(S.NT), shmem, st, A);
     pe(L.bwd ? 1 : 0);
@@ -901,11 +1182,11 @@ struct GpuExec {
   }
 
   void assemble(int seg, int nb, int sample0, const float* th, const float* xx, const float* partF, float* Gr) {
-    const long long nr = (long long)(c.seg_run_begin[seg + 1] - c.seg_run_begin[seg]) * nb;
-    if (nr == 0) return;
+    const int p0 = c.seg_begin[seg], np = c.seg_begin[seg + 1] - p0;
+    if (np == 0 || nb == 0) return;
     pb();
-    hipLaunchKernelGGL(k_assemble, dim3(blocks_for(nr, 128)), dim3(128), 0, st, d.tabs, seg, nb, sample0,
-                       c.tiles * c.waves, c.n_angle, th, xx, c.C.F, partF, Gr);
+    hipLaunchKernelGGL(k_assemble, dim3((unsigned)(nb * np)), dim3(256), sizeof(double) * 3 * std::max(1, c.S.max_slots),
+                       st, d.tabs, p0, np, nb, sample0, c.tiles, c.n_angle, th, xx, c.C.F, partF, Gr);
     pe(2);
     check("k_assemble");
   }
@@ -1162,19 +1443,20 @@ qf_status qf_plan_get_info(const qf_plan* p, qf_plan_info* info) {
   const double adj = 3 * P - 2;   // the seed pass reads no lambda, pass 0 writes none
   info->bwd_pass_bytes_per_sample = adj * SB;
   info->bwd_bytes_per_sample = (recompute + adj) * SB + (c.store ? 0 : info->fwd_bytes_per_sample);
-  // algorithmic flops: a 2x2 complex run on every amplitude pair is 16 real
-  // multiply-adds per pair (16 flops per amplitude); the adjoint applies it to
-  // psi and lambda and evaluates three functionals (6 multiply-adds per amplitude)
+  // algorithmic flops of a run: its real RY on every complex amplitude pair is 8
+  // multiply-adds per pair (8 flops per amplitude); the adjoint applies RY^dagger
+  // to psi and lambda (16 flops per amplitude) and evaluates the three
+  // functionals (6 multiply-adds, 12 flops per amplitude)
   const double runs = (double)S.n_u2;
-  info->fwd_flops_per_sample = runs * 16 * A;
+  info->fwd_flops_per_sample = runs * 8 * A;
   double rec_runs = 0;
   for (int s = 0; s < c.n_seg; ++s)
     for (int q = c.seg_begin[s]; q <= c.seg_begin[s + 1] - 2; ++q) {
       const PassRec& pr = S.passes[q];
       rec_runs += pr.n_slots;
     }
-  info->bwd_pass_flops_per_sample = runs * 44 * A;
-  info->bwd_flops_per_sample = info->bwd_pass_flops_per_sample + rec_runs * 16 * A +
+  info->bwd_pass_flops_per_sample = runs * 28 * A;
+  info->bwd_flops_per_sample = info->bwd_pass_flops_per_sample + rec_runs * 8 * A +
                                (c.store ? 0 : info->fwd_flops_per_sample);
   info->bwd_pass_launches = (int64_t)c.P * ((c.B + c.mb - 1) / c.mb);
   return QF_OK;
@@ -1218,6 +1500,8 @@ qf_status qf_backward(qf_plan* p, const float* theta, const float* x, const floa
   ex.x = x;
   ex.csh = (const float*)((char*)ws + c.off_coef_sh);
   ex.cps = (const float*)((char*)ws + c.off_coef_ps);
+  ex.esh = (const float*)((char*)ws + c.off_ev_sh);
+  ex.eps = (const float*)((char*)ws + c.off_ev_ps);
   st = run_backward(c, ex, theta, x, dE, dtheta, dx, (char*)ws);
   if (st != QF_OK) return fail(st, ex.msg);
   return QF_OK;

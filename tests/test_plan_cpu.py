@@ -96,11 +96,11 @@ def test_per_gate_programs(orc, n, L):
 
 
 def test_schedule_shape_at_benchmark_sizes():
-    """20 qubits x 1000 layers: tiles of 2^13, register blocks of 5 qubits and
-    several layers fused per HBM round trip."""
+    """20 qubits x 1000 layers: tiles of 2^12 amplitudes, register blocks of 4
+    qubits and several layers fused per HBM round trip."""
     g = hea_gates(20, 1000, ("RX", "RY", "RZ"))
     st = pc.stats(20, g, 60000, 20, [1], 1000, fusion_depth=8)
-    assert st["k"] == 13 and st["R"] == 5
+    assert st["k"] == 12 and st["R"] == 4
     assert st["runs"] == 20 * 1000          # encoding merged into layer 1
     assert st["u2"] == st["runs"]           # every run applied exactly once
     assert st["passes"] < 1000              # more than one layer per pass on average
