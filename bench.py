@@ -28,7 +28,10 @@ PEAK_HBM_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz.
 PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bwd_pass_hea20q1000l.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2603_02804_amd", "csrc", "qfuse.hip")
+# sources that decide what the pass kernels execute and read/write: when any of
+# them changes, the stored counter measurement no longer applies
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2603_02804_amd", "csrc", f)
+               for f in ("device.hpp", "kargs.hpp", "plan_types.hpp", "plan.cpp")]
 
 
 def parse():
@@ -52,8 +55,11 @@ def parse():
 
 
 def kernel_sha() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def main() -> int:
@@ -134,10 +140,13 @@ def main() -> int:
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("kernel_src_sha") == kernel_sha() and tr.get("batch") == B and not args.layers:
-            traffic = tr.get("hbm_bytes_per_launch")
+        shape = {k: getattr(info, k) for k in ("tile_qubits", "reg_qubits", "fusion_depth", "fused_passes",
+                                               "micro_batch")}
+        if tr.get("kernel_src_sha") == kernel_sha() and tr.get("plan") == shape and not args.layers:
+            # counters were taken per sample over every adjoint pass launch
+            traffic = round(tr["hbm_bytes_per_sample"] * B * args.steps / max(1, n_bwd))
     roofline = {
-        "kernel": "k_pass<5,256,bwd> (fused adjoint pass)",
+        "kernel": f"k_pass<{info.reg_qubits},{info.threads},true> (fused adjoint pass)",
         "bound": "alu", "achieved": round(achieved_tf, 2), "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
         "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
         "launches": n_bwd, "avg_launch_ms": round(prof.ms[1] / max(1, n_bwd), 4),

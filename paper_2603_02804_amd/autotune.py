@@ -1,0 +1,159 @@
+"""Autotuner: tile shape, fusion depth, checkpoint interval and micro-batch.
+
+Memory model (Sec. 3.4, eq. mem_cap_pytorch and eq. mem_cap_proposed): with
+gradient checkpointing over blocks of b layers of a d-layer circuit, a method
+that keeps s state vectors per layer of the active block needs
+    M(b) = (s b + d / b) M_sv,   minimised at b* = sqrt(d / s),
+s = l_var + l_const for per-gate storage, ceil(l_var / m) for fused gates of m
+rotations.  This build checkpoints segments of fused passes instead of layers:
+with P passes, segments of c passes, a batch B whose checkpoints are kept and a
+micro-batch mb recomputed at a time,
+    states(c) = ceil(P / c) B + (c - 1) mb + 4 mb,
+minimised near c* = sqrt(P B / mb); the exact byte count is the plan's
+qf_workspace_size.
+
+Speed: for each candidate (tile qubits, register qubits, fusion depth) the tuner
+builds a plan for a prefix of the gate list, times forward + backward with HIP
+events, and scales by the gate count.  Results are cached in a JSON file keyed
+by the circuit's shape and the device name.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+TUNED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_configs.json")
+
+# (tile qubits, register qubits) shapes with compiled kernels
+TILE_SHAPES = ((12, 4), (13, 5), (11, 4))
+FUSION_DEPTHS = (4, 8, 12, 16)
+
+
+def paper_memory_bytes(stored_per_layer: float, d: int, b: float, m_sv: int) -> float:
+    """(s b + d / b) M_sv."""
+    return (stored_per_layer * b + d / b) * m_sv
+
+
+def paper_optimal_block(stored_per_layer: float, d: int) -> float:
+    return math.sqrt(d / stored_per_layer)
+
+
+def plan_states(passes: int, ckpt: int, batch: int, micro_batch: int, store: bool = True) -> int:
+    """States held by a plan's workspace: checkpoints + one segment of pass outputs + ping-pong buffers."""
+    segs = -(-passes // ckpt)
+    kept = batch if store else micro_batch
+    return segs * kept + max(0, ckpt - 1) * micro_batch + 4 * micro_batch
+
+
+def optimal_ckpt(passes: int, batch: int, micro_batch: int, store: bool = True) -> int:
+    kept = batch if store else micro_batch
+    guess = max(1, int(round(math.sqrt(passes * kept / max(1, micro_batch)))))
+    best = min(range(max(1, guess // 2), min(passes, 2 * guess) + 1),
+               key=lambda c: (plan_states(passes, c, batch, micro_batch, store), c))
+    return best
+
+
+def circuit_key(n_qubits: int, gates: np.ndarray, n_obs: int, batch: int, device: str) -> str:
+    h = hashlib.sha256(np.ascontiguousarray(gates, dtype=np.int32)[:, :3].tobytes()).hexdigest()[:16]
+    return f"n{n_qubits}-g{len(gates)}-{h}-k{n_obs}-b{batch}-{device}"
+
+
+def _load_cache(path: str) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def cached_tuning(n_qubits, gates, n_obs, batch, device, path: str = TUNED_CACHE) -> Optional[dict]:
+    return _load_cache(path).get(circuit_key(n_qubits, gates, n_obs, batch, device))
+
+
+def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequence[int], batch: int,
+             budget_bytes: Optional[int] = None, prefix_gates: int = 6000, reps: int = 2,
+             shapes=TILE_SHAPES, depths=FUSION_DEPTHS, cache_path: Optional[str] = None,
+             log=None) -> dict:
+    """Times the candidates on the current GPU and returns the chosen tuning fields."""
+    import torch
+
+    from . import qfuse
+
+    gates = np.ascontiguousarray(gates, dtype=np.int32).reshape(-1, 5)
+    dev = torch.device("cuda")
+    name = torch.cuda.get_device_name(dev).replace(" ", "_") or "gpu"
+    G = len(gates)
+    pre = gates[: min(G, prefix_gates)]
+    P_used = int(pre[:, 3].max()) + 1 if (pre[:, 3] >= 0).any() else 0
+    theta = torch.rand(max(P_used, 1), device=dev) * 6.283
+    rng = np.random.default_rng(0)
+    results = []
+    for (k, r) in shapes:
+        if k > n_qubits and (k, r) != shapes[0]:
+            continue
+        for F in depths:
+            tun = qfuse.make_tuning(tile_qubits=k, reg_qubits=r, fusion_depth=F)
+            try:
+                circ = qfuse.Circuit(n_qubits, pre, max(P_used, 1), n_inputs, z_masks)
+                probe = qfuse.Plan(circ, 1, tun)
+                mb = probe.info.micro_batch
+                plan = qfuse.Plan(circ, mb, qfuse.make_tuning(tile_qubits=k, reg_qubits=r, fusion_depth=F,
+                                                              micro_batch=mb))
+            except qfuse.QFuseError:
+                continue
+            x = torch.tensor(rng.uniform(-3.14, 3.14, size=(mb, n_inputs)).astype(np.float32), device=dev) \
+                if n_inputs else None
+            ws = plan.new_workspace(dev)
+            dE = torch.ones(mb, len(z_masks), device=dev)
+            best = float("inf")
+            for _ in range(reps + 1):
+                s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                s0.record()
+                plan.forward(theta, x, ws)
+                plan.backward(theta, x, dE, ws)
+                s1.record()
+                torch.cuda.synchronize()
+                best = min(best, s0.elapsed_time(s1))
+            per_sample_full = best / mb * (G / len(pre))
+            results.append({"tile_qubits": k, "reg_qubits": r, "fusion_depth": F, "micro_batch": mb,
+                            "ms_per_sample": per_sample_full})
+            if log:
+                log(f"autotune k={k} r={r} F={F} mb={mb}: {per_sample_full:.3f} ms/sample")
+            del ws, plan, probe
+    if not results:
+        raise RuntimeError("no candidate tuning could be planned")
+    best = min(results, key=lambda d: d["ms_per_sample"])
+    out = {k: best[k] for k in ("tile_qubits", "reg_qubits", "fusion_depth", "micro_batch")}
+    # checkpoint interval from the memory model of the full circuit
+    circ = qfuse.Circuit(n_qubits, gates, n_params, n_inputs, z_masks)
+    probe = qfuse.Plan(circ, batch, qfuse.make_tuning(tile_qubits=out["tile_qubits"], reg_qubits=out["reg_qubits"],
+                                                      fusion_depth=out["fusion_depth"],
+                                                      micro_batch=out["micro_batch"]))
+    passes = probe.info.fused_passes
+    free = torch.cuda.mem_get_info()[0]
+    budget = budget_bytes if budget_bytes is not None else int(0.85 * free)
+    state = 8 << n_qubits
+    store = 1
+    c = optimal_ckpt(passes, batch, out["micro_batch"], True)
+    if plan_states(passes, c, batch, out["micro_batch"], True) * state > budget:
+        store = 0
+        c = optimal_ckpt(passes, batch, out["micro_batch"], False)
+    out.update({"ckpt_interval": c, "store_ckpt": store, "candidates": results, "device": name,
+                "passes": passes})
+    if cache_path:
+        cache = _load_cache(cache_path)
+        cache[circuit_key(n_qubits, gates, len(z_masks), batch, name)] = out
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return out
+
+
+def tuning_from(d: dict):
+    from . import qfuse
+    return qfuse.make_tuning(tile_qubits=d.get("tile_qubits", 0), reg_qubits=d.get("reg_qubits", 0),
+                             fusion_depth=d.get("fusion_depth", 0), ckpt_interval=d.get("ckpt_interval", 0),
+                             micro_batch=d.get("micro_batch", 0), store_ckpt=d.get("store_ckpt", -1))

@@ -1,0 +1,707 @@
+// device.hpp -- device code shared by the single-plan kernels and the merged
+// mixed-batch kernels: the fused pass body, the 2x2 run algebra and the bodies
+// of the coefficient, assembly and reduction kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "kargs.hpp"
+
+namespace qf {
+
+// Plan tables are written before the launch and only read by it: load them
+// through the constant address space so that uniform reads become scalar loads.
+template <typename T>
+__device__ __forceinline__ T cld(const T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return *(const __attribute__((address_space(4))) T*)(p);
+#else
+  return *p;
+#endif
+}
+
+// Register-bit dispatch: expands STMT with the compile-time bit J == j.
+#define QF_WITH_BIT(R, j, STMT)                      \
+  switch (j) {                                       \
+    case 0: { constexpr int J = 0; STMT; } break;    \
+    case 1: if constexpr (R > 1) { constexpr int J = 1; STMT; } break; \
+    case 2: if constexpr (R > 2) { constexpr int J = 2; STMT; } break; \
+    case 3: if constexpr (R > 3) { constexpr int J = 3; STMT; } break; \
+    case 4: if constexpr (R > 4) { constexpr int J = 4; STMT; } break; \
+    default: break;                                  \
+  }
+
+__device__ __forceinline__ uint32_t tbase(const uint32_t* tab, int t, int tb) {
+  uint32_t v = 0;
+#pragma unroll
+  for (int i = 0; i < kMaxThreadBits; ++i)
+    if (i < tb && ((t >> i) & 1)) v ^= cld(tab + i);
+  return v;
+}
+
+// Per-register-bit contributions of a layout, loaded once per op (uniform).
+template <int R>
+struct RegBits {
+  uint32_t v[R];
+  __device__ __forceinline__ void load(const uint32_t* p) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) v[j] = cld(p + j);
+  }
+  // XOR over the set bits of the compile-time register index jj
+  __device__ __forceinline__ uint32_t operator()(int jj) const {
+    uint32_t r = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+      if ((jj >> j) & 1) r ^= v[j];
+    return r;
+  }
+};
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+
+// Real rotation [[c, -s], [s, c]] on the pairs along register bit J.
+template <int R, int J>
+__device__ __forceinline__ void apply_ry(float2 (&a)[1 << R], float c, float s) {
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    if (i & (1 << J)) continue;
+    constexpr int m = 1 << J;
+    const float2 x0 = a[i], x1 = a[i | m];
+    a[i] = make_float2(fmaf(-s, x1.x, c * x0.x), fmaf(-s, x1.y, c * x0.y));
+    a[i | m] = make_float2(fmaf(s, x0.x, c * x1.x), fmaf(s, x0.y, c * x1.y));
+  }
+}
+
+// Diagonal phase on register bit J: w where the bit is 0, conj(w) where it is 1.
+template <int R, int J>
+__device__ __forceinline__ void apply_phase_reg(float2 (&a)[1 << R], float2 w) {
+  const float2 wc = make_float2(w.x, -w.y);
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) a[i] = cmul(a[i], (i & (1 << J)) ? wc : w);
+}
+
+// Im<l|X_q|a>, Im<l|Y_q|a>, Im<l|Z_q|a> over the pairs along register bit J.
+template <int R, int J>
+__device__ __forceinline__ void func3(const float2 (&a)[1 << R], const float2 (&l)[1 << R], float& fx, float& fy,
+                                      float& fz) {
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    if (i & (1 << J)) continue;
+    constexpr int m = 1 << J;
+    const float2 p0 = a[i], p1 = a[i | m], l0 = l[i], l1 = l[i | m];
+    fx = fmaf(l0.x, p1.y, fx); fx = fmaf(-l0.y, p1.x, fx); fx = fmaf(l1.x, p0.y, fx); fx = fmaf(-l1.y, p0.x, fx);
+    fy = fmaf(l1.x, p0.x, fy); fy = fmaf(l1.y, p0.y, fy); fy = fmaf(-l0.x, p1.x, fy); fy = fmaf(-l0.y, p1.y, fy);
+    fz = fmaf(l0.x, p0.y, fz); fz = fmaf(-l0.y, p0.x, fz); fz = fmaf(-l1.x, p1.y, fz); fz = fmaf(l1.y, p1.x, fz);
+  }
+}
+
+template <int NA>
+__device__ __forceinline__ void scale_all(float2 (&a)[NA], float2 p) {
+#pragma unroll
+  for (int i = 0; i < NA; ++i) a[i] = cmul(a[i], p);
+}
+
+template <int NA>
+__device__ __forceinline__ void flip_signs(float2 (&a)[NA], uint32_t sign) {
+#pragma unroll
+  for (int jj = 0; jj < NA; ++jj) {
+    const uint32_t f = (sign << (31 - jj)) & 0x80000000u;
+    a[jj].x = __uint_as_float(__float_as_uint(a[jj].x) ^ f);
+    a[jj].y = __uint_as_float(__float_as_uint(a[jj].y) ^ f);
+  }
+}
+
+// Butterfly reduce-scatter of 16 per-lane values over a wave of 64 lanes.
+// Afterwards lane L holds the wave sum of value ((L >> 2) & 15).
+__device__ __forceinline__ float wave_reduce16(float (&v)[16], int lane) {
+  {
+    const bool hi = (lane & 32) != 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const float send = hi ? v[i] : v[i + 8];
+      const float keep = hi ? v[i + 8] : v[i];
+      v[i] = keep + __shfl_xor(send, 32);
+    }
+  }
+  {
+    const bool hi = (lane & 16) != 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float send = hi ? v[i] : v[i + 4];
+      const float keep = hi ? v[i + 4] : v[i];
+      v[i] = keep + __shfl_xor(send, 16);
+    }
+  }
+  {
+    const bool hi = (lane & 8) != 0;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float send = hi ? v[i] : v[i + 2];
+      const float keep = hi ? v[i + 2] : v[i];
+      v[i] = keep + __shfl_xor(send, 8);
+    }
+  }
+  {
+    const bool hi = (lane & 4) != 0;
+    const float send = hi ? v[0] : v[1];
+    const float keep = hi ? v[1] : v[0];
+    v[0] = keep + __shfl_xor(send, 4);
+  }
+  v[0] += __shfl_xor(v[0], 2);
+  v[0] += __shfl_xor(v[0], 1);
+  return v[0];
+}
+
+__device__ __forceinline__ const float* run_coef(const KArgs& A, int ref, int sample) {
+  return ref >= 0 ? A.coef_sh + 8 * (size_t)ref : A.coef_ps + 8 * ((size_t)sample * A.n_ps + (-1 - ref));
+}
+
+__device__ __forceinline__ float2 event_coef(const KArgs& A, int ref, int sample) {
+  const float* p = ref >= 0 ? A.ev_sh + 2 * (size_t)ref : A.ev_ps + 2 * ((size_t)sample * A.n_evps + (-1 - ref));
+  return make_float2(cld(p), cld(p + 1));
+}
+
+// For register patterns jj in [0, 32): the set of jj with bit j set.
+__device__ __forceinline__ uint32_t bit_pattern(int j) {
+  return j == 0 ? 0xAAAAAAAAu : j == 1 ? 0xCCCCCCCCu : j == 2 ? 0xF0F0F0F0u : j == 3 ? 0xFF00FF00u : 0xFFFF0000u;
+}
+
+template <int R, int NT, bool BWD>
+__device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
+  extern __shared__ float2 lds[];
+  constexpr int NA = 1 << R;
+  constexpr int WAVES = NT / 64;
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int wave = t >> 6;
+  const int tb = A.tb;
+  const bool active = t < (1 << tb);
+  const int sl = item >> A.tiles_log2;
+  const int tile = item & ((1 << A.tiles_log2) - 1);
+  const int sample = A.sample0 + sl;
+  const PassRec* P = A.prec;
+
+  uint32_t tlog = 0, tin = 0, tout = 0;
+  const int nnl = cld(&P->n_nonlocal);
+  for (int i = 0; i < nnl; ++i)
+    if ((tile >> i) & 1) {
+      tlog |= 1u << cld(&P->nl_log[i]);
+      tin |= 1u << cld(&P->nl_in[i]);
+      tout |= 1u << cld(&P->nl_out[i]);
+    }
+
+  float2 a[NA];
+  float2 l[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    a[j] = make_float2(0.f, 0.f);
+    l[j] = make_float2(0.f, 0.f);
+  }
+  const int n_slots = cld(&P->n_slots);
+  // pending per-thread phase of the diagonal gates on thread-held qubits; it
+  // multiplies psi (and, in the backward, lambda as well)
+  float2 ph = make_float2(1.f, 0.f);
+  bool pend = false;
+
+  // the next op record is fetched while the current one executes
+  Op next = cld(A.ops);
+  for (int oi = 0; oi < A.n_ops; ++oi) {
+    const Op op = next;
+    if (oi + 1 < A.n_ops) next = cld(A.ops + oi + 1);
+    switch (op.kind) {
+      case OP_INIT0: {
+        const LayoutRec* L = A.layouts + op.a;
+        const uint32_t base = tlog | tbase(L->log_thr, t, tb);
+        RegBits<R> rb;
+        rb.load(L->log_reg);
+#pragma unroll
+        for (int jj = 0; jj < NA; ++jj)
+          a[jj] = make_float2((active && (base | rb(jj)) == 0u) ? 1.f : 0.f, 0.f);
+        break;
+      }
+      case OP_LOAD: {
+        const LayoutRec* L = A.layouts + op.a;
+        const uint32_t base = (op.c ? tout : tin) | tbase(L->mem_thr, t, tb);
+        RegBits<R> rb;
+        rb.load(L->mem_reg);
+        if (active) {
+          if (op.b == 0) {
+            const float2* src = reinterpret_cast<const float2*>(A.src0) + (long long)sl * A.s0;
+#pragma unroll
+            for (int jj = 0; jj < NA; ++jj) a[jj] = src[base | rb(jj)];
+          } else if constexpr (BWD) {
+            const float2* src = reinterpret_cast<const float2*>(A.src1) + (long long)sl * A.s1;
+#pragma unroll
+            for (int jj = 0; jj < NA; ++jj) l[jj] = src[base | rb(jj)];
+          }
+        }
+        break;
+      }
+      case OP_STORE: {
+        if (pend) {
+          scale_all<NA>(a, ph);
+          if constexpr (BWD) scale_all<NA>(l, ph);
+          ph = make_float2(1.f, 0.f);
+          pend = false;
+        }
+        const LayoutRec* L = A.layouts + op.a;
+        const uint32_t base = (op.c ? tout : tin) | tbase(L->mem_thr, t, tb);
+        RegBits<R> rb;
+        rb.load(L->mem_reg);
+        if (active && A.dst) {
+          float2* dst = reinterpret_cast<float2*>(A.dst) + (long long)sl * A.sd;
+          if constexpr (BWD) {
+#pragma unroll
+            for (int jj = 0; jj < NA; ++jj) dst[base | rb(jj)] = l[jj];
+          } else {
+#pragma unroll
+            for (int jj = 0; jj < NA; ++jj) dst[base | rb(jj)] = a[jj];
+          }
+        }
+        break;
+      }
+      case OP_PERM: {
+        if (pend) {
+          scale_all<NA>(a, ph);
+          if constexpr (BWD) scale_all<NA>(l, ph);
+          ph = make_float2(1.f, 0.f);
+          pend = false;
+        }
+        const LayoutRec* F = A.layouts + op.a;
+        const LayoutRec* T = A.layouts + op.b;
+        const uint32_t bf = tbase(F->lds_thr, t, tb);
+        const uint32_t bt = tbase(T->lds_thr, t, tb);
+        RegBits<R> rf, rt;
+        rf.load(F->lds_reg);
+        rt.load(T->lds_reg);
+        if (active) {
+#pragma unroll
+          for (int jj = 0; jj < NA; ++jj) lds[bf ^ rf(jj)] = a[jj];
+        }
+        __syncthreads();
+        if (active) {
+#pragma unroll
+          for (int jj = 0; jj < NA; ++jj) a[jj] = lds[bt ^ rt(jj)];
+        }
+        __syncthreads();
+        if constexpr (BWD) {
+          if (active) {
+#pragma unroll
+            for (int jj = 0; jj < NA; ++jj) lds[bf ^ rf(jj)] = l[jj];
+          }
+          __syncthreads();
+          if (active) {
+#pragma unroll
+            for (int jj = 0; jj < NA; ++jj) l[jj] = lds[bt ^ rt(jj)];
+          }
+          __syncthreads();
+        }
+        break;
+      }
+      case OP_RY: {
+        const float* cp = run_coef(A, op.b, sample);
+        const float c = cld(cp);
+        const float s = BWD ? -cld(cp + 1) : cld(cp + 1);
+        if constexpr (BWD) {
+          QF_WITH_BIT(R, op.a, (apply_ry<R, J>(a, c, s), apply_ry<R, J>(l, c, s)));
+        } else {
+          QF_WITH_BIT(R, op.a, (apply_ry<R, J>(a, c, s)));
+        }
+        break;
+      }
+      case OP_DIAGT: {
+        const LayoutRec* L = A.layouts + op.a;
+        const uint32_t x = tlog | tbase(L->log_thr, t, tb);
+        uint32_t par = 0;
+        for (int i = 0; i < op.c; ++i) {
+          const CzGroup g = cld(A.czg + op.b + i);
+          par ^= x & (x >> g.shift) & g.mask;
+        }
+        const uint32_t f = (uint32_t)(__popc(par) & 1) << 31;
+        ph.x = __uint_as_float(__float_as_uint(ph.x) ^ f);
+        ph.y = __uint_as_float(__float_as_uint(ph.y) ^ f);
+        for (int i = 0; i < op.e; ++i) {
+          const PhaseEv e = cld(A.pev + op.d + i);
+          float2 w = event_coef(A, e.ref, sample);
+          const bool conj = (((x >> e.q) & 1u) != 0u) != BWD;
+          if (conj) w.y = -w.y;
+          ph = cmul(ph, w);
+        }
+        pend = true;
+        break;
+      }
+      case OP_CZA: {
+        const CzaRec* C = A.cza + op.a;
+        const LayoutRec* L = A.layouts + op.b;
+        const uint32_t x = tlog | tbase(L->log_thr, t, tb);
+        uint32_t sign = cld(&C->sr);
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+          if (__popc(x & cld(&C->cmask[j])) & 1) sign ^= bit_pattern(j);
+        flip_signs<NA>(a, sign);
+        if constexpr (BWD) flip_signs<NA>(l, sign);
+        break;
+      }
+      case OP_PHASEA: {
+        const PhaseEv e = cld(A.pev + op.b);
+        float2 w = event_coef(A, e.ref, sample);
+        if (BWD) w.y = -w.y;
+        if constexpr (BWD) {
+          QF_WITH_BIT(R, op.a, (apply_phase_reg<R, J>(a, w), apply_phase_reg<R, J>(l, w)));
+        } else {
+          QF_WITH_BIT(R, op.a, (apply_phase_reg<R, J>(a, w)));
+        }
+        break;
+      }
+      case OP_EXPECT: {
+        if constexpr (!BWD) {
+          if (!A.do_expect) break;
+          const LayoutRec* L = A.layouts + op.a;
+          const uint32_t base = tlog | tbase(L->log_thr, t, tb);
+          RegBits<R> rb;
+          rb.load(L->log_reg);
+          for (int k0 = 0; k0 < A.K; k0 += 16) {
+            float v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = 0.f;
+#pragma unroll
+            for (int jj = 0; jj < NA; ++jj) {
+              const uint32_t x = base | rb(jj);
+              const float p = fmaf(a[jj].x, a[jj].x, a[jj].y * a[jj].y);
+#pragma unroll
+              for (int k = 0; k < 16; ++k)
+                if (k0 + k < A.K) v[k] += (__popc(x & cld(A.zmask + k0 + k)) & 1) ? -p : p;
+            }
+            const float s = wave_reduce16(v, lane);
+            const int idx = (lane >> 2) & 15;
+            if ((lane & 3) == 0 && k0 + idx < A.K)
+              A.partE[((size_t)item * WAVES + wave) * A.K + k0 + idx] = s;
+          }
+        }
+        break;
+      }
+      case OP_SEED: {
+        if constexpr (BWD) {
+          const LayoutRec* L = A.layouts + op.a;
+          const uint32_t base = tlog | tbase(L->log_thr, t, tb);
+          RegBits<R> rb;
+          rb.load(L->log_reg);
+          const float* g = A.dE + (size_t)sample * A.K;
+          // lambda = 2 c(x) psi, c(x) = sum_k g_k (-1)^{|x & z_k|}
+          float c[NA];
+#pragma unroll
+          for (int jj = 0; jj < NA; ++jj) c[jj] = 0.f;
+#pragma unroll 1
+          for (int k = 0; k < A.K; ++k) {
+            const float gk = cld(g + k);
+            const uint32_t zk = cld(A.zmask + k);
+#pragma unroll
+            for (int jj = 0; jj < NA; ++jj) c[jj] += (__popc((base | rb(jj)) & zk) & 1) ? -gk : gk;
+          }
+#pragma unroll
+          for (int jj = 0; jj < NA; ++jj) l[jj] = make_float2(2.f * c[jj] * a[jj].x, 2.f * c[jj] * a[jj].y);
+        }
+        break;
+      }
+      case OP_FUNC: {
+        if constexpr (BWD) {
+          const FuncEntry* fe = A.funcs + op.b;
+          const int m = op.a;
+          float v[16];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) v[i] = 0.f;
+#pragma unroll 1
+          for (int e = 0; e < m; ++e) {
+            float fx = 0.f, fy = 0.f, fz = 0.f;
+            const int rb = cld(&fe[e].regbit);
+            QF_WITH_BIT(R, rb, (func3<R, J>(a, l, fx, fy, fz)));
+            // place the three sums of entry e (static register indices)
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+              if (q == e) {
+                v[3 * q] = fx;
+                v[3 * q + 1] = fy;
+                v[3 * q + 2] = fz;
+              }
+          }
+          const float s = wave_reduce16(v, lane);
+          const int idx = (lane >> 2) & 15;
+          if ((lane & 3) == 0 && idx < 3 * m) {
+            const int e = idx / 3, pq = idx - 3 * e;
+            float* part = reinterpret_cast<float*>(lds + A.tile_elems);
+            part[wave * 3 * n_slots + 3 * fe[e].slot + pq] = s;
+          }
+        }
+        break;
+      }
+      default:
+        break;
+    }
+  }
+  if constexpr (BWD) {
+    // one partial sum per tile and functional: add the waves' sums
+    if (n_slots > 0) {
+      __syncthreads();
+      const float* part = reinterpret_cast<const float*>(lds + A.tile_elems);
+      for (int i = t; i < 3 * n_slots; i += NT) {
+        float acc = 0.f;
+#pragma unroll
+        for (int w = 0; w < WAVES; ++w) acc += part[w * 3 * n_slots + i];
+        A.partF[(size_t)item * 3 * n_slots + i] = acc;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// small kernels: coefficients, gradient assembly, reductions
+// ---------------------------------------------------------------------------
+struct D2 {
+  double r[4], i[4];   // row-major 2x2 complex
+};
+
+__device__ inline D2 d2_mul(const D2& a, const D2& b) {
+  D2 c;
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      double re = 0, im = 0;
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        re += a.r[2 * r + k] * b.r[2 * k + q] - a.i[2 * r + k] * b.i[2 * k + q];
+        im += a.r[2 * r + k] * b.i[2 * k + q] + a.i[2 * r + k] * b.r[2 * k + q];
+      }
+      c.r[2 * r + q] = re;
+      c.i[2 * r + q] = im;
+    }
+  return c;
+}
+
+__device__ inline D2 d2_eye() {
+  D2 u;
+  for (int i = 0; i < 4; ++i) u.r[i] = u.i[i] = 0;
+  u.r[0] = u.r[3] = 1;
+  return u;
+}
+
+__device__ inline D2 d2_rot(int kind, double phi) {
+  double s, c;
+  sincos(0.5 * phi, &s, &c);
+  D2 u;
+  for (int i = 0; i < 4; ++i) u.r[i] = u.i[i] = 0;
+  if (kind == QF_RX) { u.r[0] = c; u.i[1] = -s; u.i[2] = -s; u.r[3] = c; }
+  else if (kind == QF_RY) { u.r[0] = c; u.r[1] = -s; u.r[2] = s; u.r[3] = c; }
+  else { u.r[0] = c; u.i[0] = -s; u.r[3] = c; u.i[3] = s; }
+  return u;
+}
+
+__device__ inline D2 d2_pauli(int kind) {
+  D2 p;
+  for (int i = 0; i < 4; ++i) p.r[i] = p.i[i] = 0;
+  if (kind == QF_RX) { p.r[1] = 1; p.r[2] = 1; }
+  else if (kind == QF_RY) { p.i[1] = -1; p.i[2] = 1; }
+  else { p.r[0] = 1; p.r[3] = -1; }
+  return p;
+}
+
+__device__ inline D2 d2_dag(const D2& a) {
+  D2 d;
+  d.r[0] = a.r[0]; d.i[0] = -a.i[0];
+  d.r[1] = a.r[2]; d.i[1] = -a.i[2];
+  d.r[2] = a.r[1]; d.i[2] = -a.i[1];
+  d.r[3] = a.r[3]; d.i[3] = -a.i[3];
+  return d;
+}
+
+__device__ inline double gate_angle(const GateRec& g, const float* theta, const float* x, int F, int sample) {
+  return g.theta_idx >= 0 ? (double)theta[g.theta_idx] : (double)x[(size_t)sample * F + g.input_idx];
+}
+
+// RZ(a) RY(b) RZ(c) split of an SU(2) matrix V (V00 = e^{-i(a+c)/2} cos(b/2),
+// V10 = e^{i(a-c)/2} sin(b/2)).  Returns cos(b/2), sin(b/2), u = e^{-ia/2},
+// v = e^{-ic/2} and z = u^2 = e^{-ia}.
+struct ZYZ {
+  double cb, sb, ur, ui, vr, vi, zr, zi;
+};
+
+__device__ inline ZYZ zyz_split(const D2& V) {
+  ZYZ o;
+  const double a0 = sqrt(V.r[0] * V.r[0] + V.i[0] * V.i[0]);
+  const double b0 = sqrt(V.r[2] * V.r[2] + V.i[2] * V.i[2]);
+  const double nrm = sqrt(a0 * a0 + b0 * b0);
+  o.cb = a0 / nrm;
+  o.sb = b0 / nrm;
+  double Ar = 1, Ai = 0, Br = 1, Bi = 0;
+  if (a0 > 1e-300) { Ar = V.r[0] / a0; Ai = V.i[0] / a0; }
+  if (b0 > 1e-300) { Br = V.r[2] / b0; Bi = V.i[2] / b0; }
+  o.zr = Ar * Br + Ai * Bi;        // A conj(B)
+  o.zi = Ai * Br - Ar * Bi;
+  const double th = atan2(o.zi, o.zr);
+  double s, c;
+  sincos(0.5 * th, &s, &c);
+  o.ur = c;
+  o.ui = s;
+  o.vr = Ar * c + Ai * s;          // A conj(u)
+  o.vi = Ai * c - Ar * s;
+  return o;
+}
+
+__device__ inline D2 run_matrix(const Tabs& T, const RunRec& rr, const float* theta, const float* x, int F,
+                                int sample) {
+  D2 U = d2_eye();
+  for (int i = 0; i < rr.gate_count; ++i) {
+    const GateRec g = T.gates[T.run_gates[rr.gate_begin + i]];
+    U = d2_mul(d2_rot(g.kind, gate_angle(g, theta, x, F, sample)), U);
+  }
+  return U;
+}
+
+// Run coefficients.  zyz = 1: [cos(b/2), sin(b/2), u, v] of the RZ RY RZ split;
+// zyz = 0: the 2x2 matrix row-major (one-gate runs of the per-gate baseline).
+__device__ inline void coef_body(const CoefArgs& a, long long idx) {
+  if (idx >= a.n_sh + (long long)a.n_ps * a.B) return;
+  int r, sample;
+  float* out;
+  if (idx < a.n_sh) {
+    r = a.T.coef_runs_sh[idx];
+    sample = 0;
+    out = a.csh + 8 * idx;
+  } else {
+    const long long j = idx - a.n_sh;
+    sample = (int)(j / a.n_ps);
+    const int i = (int)(j - (long long)sample * a.n_ps);
+    r = a.T.coef_runs_ps[i];
+    out = a.cps + 8 * j;
+  }
+  const D2 U = run_matrix(a.T, a.T.runs[r], a.theta, a.x, a.F, sample);
+  if (a.zyz) {
+    const ZYZ z = zyz_split(U);
+    out[0] = (float)z.cb; out[1] = (float)z.sb;
+    out[2] = (float)z.ur; out[3] = (float)z.ui;
+    out[4] = (float)z.vr; out[5] = (float)z.vi;
+    out[6] = 0.f; out[7] = 0.f;
+  } else {
+    for (int i = 0; i < 4; ++i) {
+      out[2 * i] = (float)U.r[i];
+      out[2 * i + 1] = (float)U.i[i];
+    }
+  }
+}
+
+// Phase event coefficients w = u(prev run) * v(next run).
+__device__ inline void event_body(const EventArgs& a, long long idx) {
+  if (idx >= a.n_ev_sh + (long long)a.n_ev_ps * a.B) return;
+  int sample = 0;
+  EventRec e;
+  float* out;
+  if (idx < a.n_ev_sh) {
+    e = a.T.events[idx];
+    out = a.esh + 2 * idx;
+  } else {
+    const long long j = idx - a.n_ev_sh;
+    sample = (int)(j / a.n_ev_ps);
+    const int i = (int)(j - (long long)sample * a.n_ev_ps);
+    e = a.T.events[a.n_ev_sh + i];
+    out = a.eps + 2 * j;
+  }
+  auto row = [&](int ref) {
+    return ref >= 0 ? a.csh + 8 * (long long)ref : a.cps + 8 * ((long long)sample * a.n_ps + (-1 - ref));
+  };
+  float wr = 1.f, wi = 0.f;
+  if (e.prev_ref != INT32_MIN) {
+    const float* p = row(e.prev_ref);
+    const float ur = p[2], ui = p[3];
+    const float tr = wr * ur - wi * ui, ti = wr * ui + wi * ur;
+    wr = tr; wi = ti;
+  }
+  if (e.next_ref != INT32_MIN) {
+    const float* p = row(e.next_ref);
+    const float vr = p[4], vi = p[5];
+    const float tr = wr * vr - wi * vi, ti = wr * vi + wi * vr;
+    wr = tr; wi = ti;
+  }
+  out[0] = wr;
+  out[1] = wi;
+}
+
+// Gradients of the gates of run r from the functionals F = Im<lambda|P_q|psi>
+// (P = X, Y, Z) taken at the cut right after the run's RY (zyz = 1) or right
+// after the whole run (zyz = 0).  dL/dtheta_g = 1/2 Im<lambda|G|psi>, with G the
+// generator of gate g carried to the cut: G = K P_g K^dagger (K = gates of the
+// run after g), conjugated by RZ(a)^dagger for the zyz cut.  Writing
+// G = n_x X + n_y Y + n_z Z gives dL/dtheta_g = 1/2 (n . F).
+__device__ inline void run_grads(const Tabs& T, int r, const float* theta, const float* x, int F, int sample,
+                                 double fx, double fy, double fz, float* Grow, int zyz) {
+  const RunRec rr = T.runs[r];
+  double zr = 1, zi = 0;
+  if (zyz) {
+    const ZYZ z = zyz_split(run_matrix(T, rr, theta, x, F, sample));
+    zr = z.zr;
+    zi = z.zi;
+  }
+  D2 K = d2_eye();
+  for (int i = rr.gate_count - 1; i >= 0; --i) {
+    const GateRec g = T.gates[T.run_gates[rr.gate_begin + i]];
+    const D2 G = d2_mul(d2_mul(K, d2_pauli(g.kind)), d2_dag(K));
+    const double gr = zr * G.r[2] - zi * G.i[2], gi = zr * G.i[2] + zi * G.r[2];
+    Grow[g.out_idx] = (float)(0.5 * (gr * fx + gi * fy + G.r[0] * fz));
+    K = d2_mul(K, d2_rot(g.kind, gate_angle(g, theta, x, F, sample)));
+  }
+}
+
+// One block per (sample, pass of the segment): sum the pass's per-tile
+
+// One block per (sample, pass of the segment): sum the pass's per-tile
+// functional partials (coalesced over the slots), then one thread per run turns
+// the three sums into the run's per-gate gradients.  fsum: 3 * max_slots doubles
+// of LDS.
+__device__ inline void assemble_body(const AssembleArgs& a, int blk, double* fsum) {
+  const int s = blk / a.np, p = a.p0 + (blk - s * a.np);
+  const int ns = a.T.passes[p].n_slots;
+  if (ns == 0) return;
+  const float* base = a.partF + (long long)a.nb * a.T.partF_off[p] + (long long)s * a.tiles * 3 * ns;
+  for (int v = threadIdx.x; v < 3 * ns; v += blockDim.x) {
+    double acc = 0;
+    for (int tile = 0; tile < a.tiles; ++tile) acc += base[(long long)tile * 3 * ns + v];
+    fsum[v] = acc;
+  }
+  __syncthreads();
+  const int rb = a.T.pass_run_begin[p];
+  for (int i = threadIdx.x; i < ns; i += blockDim.x)
+    run_grads(a.T, a.T.pass_runs[rb + i], a.theta, a.x, a.F, a.sample0 + s, fsum[3 * i], fsum[3 * i + 1],
+              fsum[3 * i + 2], a.Gr + (long long)s * a.n_angle, 1);
+}
+
+// theta: sum over the micro-batch and over the gates sharing the angle; x: sum
+// over the gates sharing the input, per sample.  Fixed order.
+__device__ inline void reduce_grads_body(const ReduceGArgs& a, long long idx) {
+  if (idx < a.P) {
+    const int p = (int)idx;
+    double acc = 0;
+    for (int s = 0; s < a.nb; ++s)
+      for (int i = a.T.th_ref_begin[p]; i < a.T.th_ref_begin[p + 1]; ++i)
+        acc += a.Gr[(long long)s * a.n_angle + a.T.th_refs[i]];
+    a.dtheta[p] = a.accumulate ? a.dtheta[p] + (float)acc : (float)acc;
+  } else if (a.dx && idx < a.P + (long long)a.nb * a.F) {
+    const long long j = idx - a.P;
+    const int s = (int)(j / a.F), f = (int)(j - (long long)s * a.F);
+    double acc = 0;
+    for (int i = a.T.in_ref_begin[f]; i < a.T.in_ref_begin[f + 1]; ++i)
+      acc += a.Gr[(long long)s * a.n_angle + a.T.in_refs[i]];
+    a.dx[(long long)(a.sample0 + s) * a.F + f] = (float)acc;
+  }
+}
+
+__device__ inline void reduce_E_body(const ReduceEArgs& a, long long idx) {
+  if (idx >= (long long)a.nb * a.K) return;
+  const int s = (int)(idx / a.K), k = (int)(idx - (long long)s * a.K);
+  double acc = 0;
+  for (int i = 0; i < a.parts; ++i) acc += a.partE[((long long)s * a.parts + i) * a.K + k];
+  a.E[(long long)(a.sample0 + s) * a.K + k] = (float)acc;
+}
+
+}  // namespace qf

@@ -1,0 +1,141 @@
+"""Full-size configurations on the GPU, in the launch configuration bench.py uses.
+
+* 16 qubits x 200 layers (RX,RY,RZ + CZ ladder), batch 512, <Z_0..Z_3> -> 4-class
+  cross-entropy through CircuitFunction: sampled samples against the live oracle,
+  the autograd gradient against the parameter-shift rule (exact for Pauli
+  rotations) and against central finite differences of the loss.
+* 20 qubits x 1000 layers, batch 1000: samples 0 and 1 against stored oracle
+  values (tests/golden/make_hea20q1000l_oracle.py); the all-zero-angle closed form
+  <Z_i> = cos x_i, dL/dx_i = -g_i sin x_i at full depth.
+Tolerances as in test_gpu_parity: |dE| <= 1e-4, normwise gradient error <= 1e-3.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.oracle import Oracle, loss_and_grad_E  # noqa: E402
+from paper_2603_02804_amd import qfuse  # noqa: E402
+from paper_2603_02804_amd.workloads import c3, c4  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+E_TOL = 1e-4
+G_TOL = 1e-3
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "hea20q1000l_oracle_2samples.npz")
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a, np.float64) - b).max() / np.abs(b).max())
+
+
+def ce_autograd(w, plan, dev, theta_np=None):
+    theta = torch.tensor(w.theta if theta_np is None else theta_np, device=dev, requires_grad=True)
+    x = torch.tensor(w.x, device=dev, requires_grad=True)
+    E = qfuse.circuit_expectations(theta, x, plan)
+    loss = torch.nn.functional.cross_entropy(E, torch.tensor(w.labels, device=dev))
+    loss.backward()
+    torch.cuda.synchronize()
+    return E.detach(), float(loss), theta.grad.cpu().numpy(), x.grad.cpu().numpy()
+
+
+def ce_loss(w, plan, dev, theta_np):
+    theta = torch.tensor(theta_np, device=dev)
+    x = torch.tensor(w.x, device=dev)
+    ws = plan.new_workspace(dev)
+    E = plan.forward(theta, x, ws).double()
+    return float(torch.nn.functional.cross_entropy(E, torch.tensor(w.labels, device=dev)))
+
+
+@pytest.mark.timeout(600)
+def test_hea16q200l_ce():
+    w = c3()
+    dev = torch.device("cuda:0")
+    circ = qfuse.Circuit(w.n_qubits, w.gates, w.n_params, w.n_inputs, w.zmask)
+    plan = qfuse.Plan(circ, w.batch)
+    E, loss, dth, dx = ce_autograd(w, plan, dev)
+    # sampled samples against the oracle, with the full-batch normalisation
+    orc = Oracle()
+    idx = [0, 1]
+    Eo = orc.forward(w.n_qubits, w.gates, w.theta, w.x[idx], w.xmask, w.zmask)
+    assert np.abs(E.cpu().numpy()[idx] - Eo).max() <= E_TOL
+    _, gE = loss_and_grad_E(Eo, "ce", w.labels[idx])
+    gE *= len(idx) / w.batch
+    _, dtho, dxo = orc.backward(w.n_qubits, w.gates, w.theta, w.x[idx], w.xmask, w.zmask, gE)
+    assert rel(dx[idx], dxo) <= G_TOL
+    # dtheta of the same two samples through the C-ABI
+    sub = qfuse.Plan(circ, len(idx))
+    ws = sub.new_workspace(dev)
+    th = torch.tensor(w.theta, device=dev)
+    xs = torch.tensor(w.x[idx], device=dev)
+    sub.forward(th, xs, ws)
+    dth2, _ = sub.backward(th, xs, torch.tensor(gE, dtype=torch.float32, device=dev), ws)
+    assert rel(dth2.cpu().numpy(), dtho) <= G_TOL
+    # autograd gradient of the full-batch loss: parameter shift on dE/dtheta_p
+    # (exact for exp(-i phi P/2)) chained with dL/dE, and central differences
+    Ed = E.double().requires_grad_(True)
+    torch.nn.functional.cross_entropy(Ed, torch.tensor(w.labels, device=dev)).backward()
+    gLE = Ed.grad
+    rng = np.random.default_rng(3)
+    for p in rng.choice(w.n_params, size=3, replace=False):
+        tp, tm = w.theta.copy(), w.theta.copy()
+        tp[p] += np.float32(math.pi / 2)
+        tm[p] -= np.float32(math.pi / 2)
+        ws2 = plan.new_workspace(dev)
+        Ep = plan.forward(torch.tensor(tp, device=dev), torch.tensor(w.x, device=dev), ws2).double()
+        Em = plan.forward(torch.tensor(tm, device=dev), torch.tensor(w.x, device=dev), ws2).double()
+        shift = float((gLE * (Ep - Em) / 2).sum())
+        h = 2e-2
+        tp, tm = w.theta.astype(np.float64).copy(), w.theta.astype(np.float64).copy()
+        tp[p] += h
+        tm[p] -= h
+        fd = (ce_loss(w, plan, dev, tp.astype(np.float32)) - ce_loss(w, plan, dev, tm.astype(np.float32))) / (
+            float(np.float32(tp[p])) - float(np.float32(tm[p])))
+        scale = np.abs(dth).max()
+        assert abs(dth[p] - shift) <= G_TOL * scale
+        assert abs(dth[p] - fd) <= 5e-3 * scale
+
+
+@pytest.mark.timeout(900)
+def test_hea20q1000l_sampled():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("stored oracle values not generated")
+    g = np.load(GOLDEN)
+    w = c4()
+    dev = torch.device("cuda:0")
+    circ = qfuse.Circuit(w.n_qubits, w.gates, w.n_params, w.n_inputs, w.zmask)
+    plan = qfuse.Plan(circ, w.batch)
+    E, loss, dth, dx = ce_autograd(w, plan, dev)
+    idx = list(g["samples"])
+    assert np.abs(E.cpu().numpy()[idx] - g["E"]).max() <= E_TOL
+    assert rel(dx[idx], g["dx"]) <= G_TOL
+    sub = qfuse.Plan(circ, len(idx))
+    ws = sub.new_workspace(dev)
+    th = torch.tensor(w.theta, device=dev)
+    xs = torch.tensor(w.x[idx], device=dev)
+    sub.forward(th, xs, ws)
+    dth2, _ = sub.backward(th, xs, torch.tensor(g["dE"], dtype=torch.float32, device=dev), ws)
+    assert rel(dth2.cpu().numpy(), g["dtheta"]) <= G_TOL
+
+
+@pytest.mark.timeout(600)
+def test_hea20q1000l_zero_angles():
+    """All variational angles zero: E_i = cos x_i and dL/dx_i = -g_i sin x_i exactly."""
+    w = c4(batch_override=16)
+    dev = torch.device("cuda:0")
+    circ = qfuse.Circuit(w.n_qubits, w.gates, w.n_params, w.n_inputs, w.zmask)
+    plan = qfuse.Plan(circ, w.batch)
+    ws = plan.new_workspace(dev)
+    th = torch.zeros(w.n_params, device=dev)
+    x = torch.tensor(w.x, device=dev)
+    E = plan.forward(th, x, ws).cpu().numpy()
+    gE = np.random.default_rng(1).normal(size=E.shape).astype(np.float32)
+    _, dx = plan.backward(th, x, torch.tensor(gE, device=dev), ws)
+    xs = w.x[:, :10].astype(np.float64)
+    assert np.abs(E - np.cos(xs)).max() <= E_TOL
+    ref = np.zeros_like(w.x, dtype=np.float64)
+    ref[:, :10] = -gE * np.sin(xs)
+    assert rel(dx.cpu().numpy(), ref) <= G_TOL
