@@ -37,6 +37,9 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_2603_02804_amd", "csrc", f)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="hea20q1000l", choices=("hea20q1000l", "mixed256"),
+                    help="hea20q1000l: the headline 20-qubit, 1000-layer HEA; mixed256: 256 mixed circuits, "
+                         "one merged HIP graph vs per-circuit launches")
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=0, help="override the batch (exploration only)")
@@ -88,6 +91,8 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload == "mixed256":
+        return bench_mixed(args, dev)
     if args.layers:
         w = make_workload("hea20q", 20, args.layers, ("RX", "RY", "RZ"), 1000, tuple(range(10)), "ce", 4)
     else:
@@ -220,6 +225,92 @@ def main() -> int:
                                "kind": "oracle",
                                "sample": f"1 sample, first {Ls} of {w.n_layers} layers ({tL:.1f} s), "
                                          f"extrapolated linearly in depth"}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_mixed(args, dev) -> int:
+    """256 circuits, qubits ~ U{10..18}, layers ~ U{50..500} (RY,RZ + CZ ladder), 4 samples each,
+    L = sum of <Z_0>: forward + adjoint gradient of every circuit in one step."""
+    import numpy as np
+    import torch
+
+    from paper_2603_02804_amd import qfuse
+    from paper_2603_02804_amd.workloads import c5, z_observables
+
+    ws = c5()
+    xm, zm = z_observables([0])
+    circs = [qfuse.Circuit(c.n_qubits, c.gates, len(c.theta), c.n_qubits, zm) for c in ws]
+    samples = [c.x.shape[0] for c in ws]
+    thetas = [torch.tensor(c.theta, device=dev) for c in ws]
+    xs = [torch.tensor(c.x, device=dev) for c in ws]
+    dEs = [torch.ones(s, 1, device=dev) for s in samples]
+    t0 = time.perf_counter()
+    batch = qfuse.Batch(circs, samples)
+    t_create = time.perf_counter() - t0
+    info = batch.info
+    wsb = batch.new_workspace(dev)
+    n_samples = int(info.samples)
+
+    def step():
+        batch.forward(thetas, xs, wsb)
+        batch.backward(thetas, xs, dEs, wsb)
+
+    def timed(mode, steps, warmup):
+        batch.set_launch_mode(mode)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    sec = timed(qfuse.QF_LAUNCH_GRAPH, args.steps, args.warmup)
+    out = {
+        "metric": "samples/s fwd+adjoint grad, 256 mixed circuits (10-18 qubits, 50-500 layers), one merged "
+                  "HIP graph vs per-circuit launches",
+        "value": round(n_samples / sec, 2), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1000 * sec, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "mixed256: 256 HEA circuits (RY,RZ + CZ ladder), qubits ~ U{10..18}, "
+                               "layers ~ U{50..500}, 4 samples each, <Z_0>, L = sum E",
+                   "circuits": len(ws), "samples": n_samples, "fwd_launches": int(info.fwd_launches),
+                   "bwd_launches": int(info.bwd_launches), "fwd_jobs": int(info.fwd_jobs),
+                   "bwd_jobs": int(info.bwd_jobs), "fwd_steps": int(info.fwd_steps),
+                   "bwd_steps": int(info.bwd_steps), "create_s": round(t_create, 2)},
+    }
+    flops = info.fwd_flops + info.bwd_flops
+    byts = info.fwd_bytes + info.bwd_bytes
+    out["roofline"] = {"kernel": "whole call (merged pass and small kernels)", "bound": "alu",
+                       "achieved": round(flops / sec / 1e12, 2), "peak": round(PEAK_FP32_TFLOPS, 1),
+                       "unit": "TFLOP/s", "frac": round(flops / sec / 1e12 / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                       "hbm_gbs": round(byts / sec / 1e9, 1)}
+    if not args.no_baselines:
+        sec_m = timed(qfuse.QF_LAUNCH_MERGED, 1, 1)
+        sec_p = timed(qfuse.QF_LAUNCH_PER_CIRCUIT, 1, 1)
+        out["merged_eager"] = {"value": round(n_samples / sec_m, 2), "unit": "samples/s"}
+        out["per_circuit"] = {"value": round(n_samples / sec_p, 2), "unit": "samples/s",
+                              "speedup_graph": round(sec_p / sec, 2)}
+        # CPU oracle: whole circuits in order until the time budget is used, extrapolated by 2^n x gates
+        from oracle.oracle import Oracle
+        orc = Oracle()
+        work_all = sum(float(2 ** c.n_qubits) * len(c.gates) * c.x.shape[0] for c in ws)
+        done_work, spent, items = 0.0, 0.0, 0
+        for c in ws:
+            if spent > args.cpu_seconds:
+                break
+            t = time.perf_counter()
+            orc.backward(c.n_qubits, c.gates, c.theta, c.x[:1], xm, zm, np.ones((1, 1)))
+            spent += time.perf_counter() - t
+            done_work += float(2 ** c.n_qubits) * len(c.gates)
+            items += 1
+        per_work = spent / done_work
+        out["cpu_baseline"] = {"value": round(n_samples / (per_work * work_all), 4), "unit": "samples/s",
+                               "cores": orc.num_threads, "kind": "oracle",
+                               "sample": f"1 sample of each of the first {items} circuits ({spent:.1f} s), "
+                                         f"extrapolated by amplitudes x gates"}
     print(json.dumps(out), flush=True)
     return 0
 

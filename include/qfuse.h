@@ -160,6 +160,72 @@ typedef struct {
 qf_status qf_profile_enable(qf_plan* plan, int enable);
 qf_status qf_profile_read(qf_plan* plan, qf_profile* out);
 
+/*
+ * Mixed batches: many different circuits, each with its own parameters, inputs
+ * and sample count, simulated together.  Every circuit computes exactly what
+ * qf_forward / qf_backward compute for it alone (same sections of the method,
+ * same plan, same kernels and the same rounding); only the launches are shared.
+ * Each circuit's launch sequence is merged step by step with the others, so one
+ * device launch runs the step's pass of every circuit at that step, and the
+ * whole merged sequence can be replayed as one HIP graph.
+ *
+ * Ownership: the batch owns one plan per circuit, the merged launch tables on
+ * the device and a small pinned host buffer; the circuits may be destroyed after
+ * qf_batch_create.  The caller owns every buffer passed to the calls.
+ */
+typedef struct qf_batch qf_batch;
+
+typedef enum {
+  QF_LAUNCH_GRAPH = 0,        /* merged launches, captured once per workspace address
+                                 into a HIP graph and replayed (default)              */
+  QF_LAUNCH_MERGED = 1,       /* the same merged launches, issued one by one          */
+  QF_LAUNCH_PER_CIRCUIT = 2   /* each circuit's own launches, circuit after circuit
+                                 (the unmerged reference point)                       */
+} qf_launch_mode;
+
+typedef struct {
+  int32_t n_circuits;
+  int64_t samples;             /* sum over circuits                                   */
+  int32_t fwd_steps, bwd_steps;          /* longest launch sequence of one circuit    */
+  int64_t fwd_launches, bwd_launches;    /* merged launches per call                  */
+  int64_t fwd_jobs, bwd_jobs;            /* launches when circuits run one by one     */
+  double fwd_bytes, bwd_bytes;           /* algorithmic HBM bytes of one call, summed */
+  double fwd_flops, bwd_flops;           /* algorithmic fp32 flops of one call, summed */
+} qf_batch_info;
+
+/*
+ * circuits[i] is simulated for samples[i] >= 1 samples.  tuning (may be NULL)
+ * applies to every circuit's plan; mode must be 0 (fused).  The plans and merged
+ * tables live on the current HIP device.
+ */
+qf_status qf_batch_create(const qf_circuit* const* circuits, const int32_t* samples, int32_t n_circuits,
+                          const qf_tuning* tuning, qf_batch** out);
+qf_status qf_batch_destroy(qf_batch* batch);
+qf_status qf_batch_get_info(const qf_batch* batch, qf_batch_info* info);
+/* One device workspace for the whole batch (256-byte aligned start expected). */
+qf_status qf_batch_workspace_size(const qf_batch* batch, size_t* bytes);
+qf_status qf_batch_set_launch_mode(qf_batch* batch, int32_t mode);
+
+/*
+ * Forward of every circuit.  theta, x and E are HOST arrays of n_circuits
+ * DEVICE pointers: theta[i] float[n_params_i], x[i] float[samples_i][n_inputs_i]
+ * (NULL allowed when n_inputs_i == 0), E[i] float[samples_i][n_obs_i],
+ * overwritten.  The batch copies the pointer arrays before returning.
+ * Calls on one batch must be ordered (one stream, or synchronised streams).
+ */
+qf_status qf_batch_forward(qf_batch* batch, const float* const* theta, const float* const* x,
+                           float* const* E, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Backward of every circuit after qf_batch_forward with the same ws, theta and
+ * x.  dE[i] float[samples_i][n_obs_i]; dtheta[i] float[n_params_i] (overwritten,
+ * summed over the circuit's samples); dx may be NULL, or dx[i] NULL, or
+ * dx[i] float[samples_i][n_inputs_i] (overwritten).
+ */
+qf_status qf_batch_backward(qf_batch* batch, const float* const* theta, const float* const* x,
+                            const float* const* dE, float* const* dtheta, float* const* dx, void* ws,
+                            size_t ws_bytes, void* stream);
+
 const char* qf_status_string(qf_status status);
 /* Detail of the last error on the calling thread ("" if none). */
 const char* qf_last_error(void);

@@ -31,10 +31,26 @@ def _run(cmd):
         raise RuntimeError(f"build failed: {' '.join(cmd)}")
 
 
+HIP_SOURCES = ("plan.cpp", "qfuse.hip", "batch.hip")
+
+
 def build_hip(out: str = LIB) -> str:
-    srcs = [os.path.join(CSRC, "plan.cpp"), os.path.join(CSRC, "qfuse.hip")]
+    """Compiles every source to an object in parallel, then links the library."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in HIP_FLAGS if f != "-shared"]
+    jobs = []
+    for src in HIP_SOURCES:
+        obj = os.path.join(objdir, src + ".o")
+        jobs.append((obj, [HIPCC, *compile_flags, f"-I{INCLUDE}", f"-I{CSRC}", "-c", os.path.join(CSRC, src),
+                           "-o", obj]))
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        for f in [ex.submit(_run, cmd) for _, cmd in jobs]:
+            f.result()
     tmp = out + ".tmp"
-    _run([HIPCC, *HIP_FLAGS, f"-I{INCLUDE}", f"-I{CSRC}", *srcs, "-o", tmp])
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *[o for o, _ in jobs], "-o", tmp])
     os.replace(tmp, out)
     return out
 

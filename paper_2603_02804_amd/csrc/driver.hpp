@@ -289,8 +289,7 @@ void forward_passes(const PlanCore& c, Exec& ex, char* ws, int mb0, int nb, bool
 }
 
 template <class Exec>
-qf_status run_forward(const PlanCore& c, Exec& ex, const float* theta, const float* x, float* E, char* ws) {
-  if (c.per_gate) return run_forward_pg(c, ex, theta, x, E, ws);
+qf_status run_forward_fused(const PlanCore& c, Exec& ex, const float* theta, const float* x, float* E, char* ws) {
   const int64_t SA = 2 * c.amps;
   ex.coef(theta, x, ws);
   for (int mb0 = 0; mb0 < c.B; mb0 += c.mb) {
@@ -303,9 +302,8 @@ qf_status run_forward(const PlanCore& c, Exec& ex, const float* theta, const flo
 }
 
 template <class Exec>
-qf_status run_backward(const PlanCore& c, Exec& ex, const float* theta, const float* x, const float* dE,
-                       float* dtheta, float* dx, char* ws) {
-  if (c.per_gate) return run_backward_pg(c, ex, theta, x, dE, dtheta, dx, ws);
+qf_status run_backward_fused(const PlanCore& c, Exec& ex, const float* theta, const float* x, const float* dE,
+                             float* dtheta, float* dx, char* ws) {
   const int64_t SA = 2 * c.amps;
   float* seg = at<float>(ws, c.off_seg);
   float* lam = at<float>(ws, c.off_lam);
@@ -356,6 +354,19 @@ qf_status run_backward(const PlanCore& c, Exec& ex, const float* theta, const fl
     ex.reduce_grads(nb, mb0, Gr, dtheta, dx, mb0 > 0);
   }
   return ex.status();
+}
+
+template <class Exec>
+qf_status run_forward(const PlanCore& c, Exec& ex, const float* theta, const float* x, float* E, char* ws) {
+  if (c.per_gate) return run_forward_pg(c, ex, theta, x, E, ws);
+  return run_forward_fused(c, ex, theta, x, E, ws);
+}
+
+template <class Exec>
+qf_status run_backward(const PlanCore& c, Exec& ex, const float* theta, const float* x, const float* dE,
+                       float* dtheta, float* dx, char* ws) {
+  if (c.per_gate) return run_backward_pg(c, ex, theta, x, dE, dtheta, dx, ws);
+  return run_backward_fused(c, ex, theta, x, dE, dtheta, dx, ws);
 }
 
 }  // namespace qf

@@ -285,7 +285,7 @@ struct CircPtrs {
 struct PassJob {
   KArgs A;
   int32_t circ;
-  int32_t pad;
+  int32_t pass;       // pass index in the circuit's plan (host checks only)
 };
 
 enum SmallKind : int32_t { SJ_COEF = 0, SJ_EVENT = 1, SJ_REDUCE_E = 2, SJ_ASSEMBLE = 3, SJ_REDUCE_G = 4 };

@@ -13,6 +13,9 @@
 #include <string>
 #include <vector>
 
+#include <memory>
+
+#include "batch.hpp"
 #include "driver.hpp"
 
 namespace qf {
@@ -659,6 +662,119 @@ int qfc_stats(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tunin
                    pc.S.n_diag_amp};
   for (int i = 0; i < n_out && i < 14; ++i) out[i] = v[i];
   return 0;
+}
+
+// Mixed batch on the CPU: builds every circuit's plan, records and merges the
+// launch sequences exactly as the device library does, checks every job's
+// workspace extents, then replays the merged launches job by job with the
+// emulated kernels.  Outputs must equal qfc_run of each circuit alone.
+// stats (8): fwd_steps, bwd_steps, fwd_launches, bwd_launches, fwd_jobs,
+// bwd_jobs, ws_bytes, max jobs in one launch.
+int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, int32_t n, const qf_tuning* tuning,
+                  const float* const* theta, const float* const* x, const float* const* dE, float* const* E,
+                  float* const* dtheta, float* const* dx, int64_t* stats) {
+  try {
+    std::string msg;
+    Tuning T;
+    if (tuning) {
+      T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
+      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt;
+    }
+    std::vector<std::unique_ptr<PlanCore>> pcs;
+    std::vector<const PlanCore*> cores;
+    std::vector<PlanPtrs> ptrs;
+    for (int i = 0; i < n; ++i) {
+      qf_status st = validate_circuit(descs[i], &msg);
+      if (st != QF_OK) { g_err = msg; return st; }
+      Circuit C;
+      C.n = descs[i]->n_qubits; C.P = descs[i]->n_params; C.F = descs[i]->n_inputs; C.K = descs[i]->n_obs;
+      C.gates.assign(descs[i]->gates, descs[i]->gates + descs[i]->n_gates);
+      C.obs.assign(descs[i]->obs, descs[i]->obs + descs[i]->n_obs);
+      pcs.emplace_back(new PlanCore);
+      st = build_plan_core(C, samples[i], T, pcs.back().get(), &msg);
+      if (st != QF_OK) { g_err = msg; return st; }
+      const PlanCore& c = *pcs.back();
+      cores.push_back(&c);
+      PlanPtrs pp;   // host copies of the tables: only their addresses enter the jobs
+      pp.ops = c.S.ops.data(); pp.layouts = c.S.layouts.data(); pp.czg = c.S.czg.data();
+      pp.funcs = c.S.funcs.data(); pp.passes = c.S.passes.data(); pp.pev = c.S.pev.data(); pp.cza = c.S.cza.data();
+      ptrs.push_back(pp);
+    }
+    std::vector<uint64_t> off;
+    const uint64_t ws_bytes = batch_layout(cores, &off);
+    std::vector<CircProgram> fwd, bwd;
+    record_programs(cores, ptrs, off, &fwd, &bwd);
+    std::vector<Region> regions;
+    for (int i = 0; i < n; ++i) regions.push_back({off[i], off[i] + cores[i]->ws_bytes});
+    if (!check_program(fwd, cores, regions, &msg) || !check_program(bwd, cores, regions, &msg)) {
+      g_err = msg;
+      return QF_ERR_INTERNAL;
+    }
+    const std::vector<int> order = batch_order(cores);
+    Program pf, pb;
+    if (!merge_programs(fwd, order, &pf, &msg) || !merge_programs(bwd, order, &pb, &msg)) {
+      g_err = msg;
+      return QF_ERR_UNSUPPORTED;
+    }
+    std::vector<char> ws(ws_bytes, 0);
+    char* base = ws.data();
+    std::vector<std::unique_ptr<CpuExec>> ex;
+    for (int i = 0; i < n; ++i) {
+      ex.emplace_back(new CpuExec(*cores[i]));
+      ex.back()->ws_lo = base + off[i];
+      ex.back()->ws_hi = base + off[i] + cores[i]->ws_bytes;
+    }
+    auto rb = [&](auto p) { return p ? reinterpret_cast<decltype(p)>(base + reinterpret_cast<uintptr_t>(p)) : p; };
+    auto replay = [&](const Program& P) {
+      for (const MergedLaunch& L : P.launches) {
+        for (int q = 0; q < L.n_jobs; ++q) {
+          if (L.cls >= 0) {
+            const PassJob& j = P.pjobs[L.job0 + q];
+            PassLaunch pl = P.plaunch[L.job0 + q];
+            pl.src0 = rb(pl.src0);
+            pl.src1 = rb(pl.src1);
+            pl.dst = rb(pl.dst);
+            pl.partF = rb(pl.partF);
+            pl.partE = rb(pl.partE);
+            pl.dE = dE ? dE[j.circ] : nullptr;
+            ex[j.circ]->pass(pl);
+            continue;
+          }
+          const SmallJob& j = P.sjobs[L.job0 + q];
+          CpuExec& e = *ex[j.circ];
+          const int c = j.circ;
+          switch (j.kind) {
+            case SJ_COEF: e.coef(theta[c], x[c], base + off[c]); break;
+            case SJ_EVENT: break;   // the emulated coefficient step also fills the phase events
+            case SJ_REDUCE_E: e.reduce_E(j.u.re.nb, j.u.re.sample0, rb(j.u.re.partE), E[c]); break;
+            case SJ_ASSEMBLE:
+              e.assemble(j.u.as.p0 / cores[c]->ckpt, j.u.as.nb, j.u.as.sample0, theta[c], x[c], rb(j.u.as.partF),
+                         rb(j.u.as.Gr));
+              break;
+            case SJ_REDUCE_G:
+              e.reduce_grads(j.u.rg.nb, j.u.rg.sample0, rb(j.u.rg.Gr), dtheta[c], dx ? dx[c] : nullptr,
+                             j.u.rg.accumulate != 0);
+              break;
+            default: throw std::runtime_error("unknown small job");
+          }
+        }
+      }
+    };
+    replay(pf);
+    if (dE) replay(pb);
+    if (stats) {
+      int64_t mx = 0;
+      for (const MergedLaunch& L : pf.launches) mx = std::max<int64_t>(mx, L.n_jobs);
+      for (const MergedLaunch& L : pb.launches) mx = std::max<int64_t>(mx, L.n_jobs);
+      const int64_t v[8] = {pf.steps, pb.steps, (int64_t)pf.launches.size(), (int64_t)pb.launches.size(), pf.jobs,
+                            pb.jobs, (int64_t)ws_bytes, mx};
+      for (int i = 0; i < 8; ++i) stats[i] = v[i];
+    }
+    return 0;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    return QF_ERR_INTERNAL;
+  }
 }
 
 const char* qfc_last_error(void) { return g_err.c_str(); }

@@ -64,6 +64,18 @@ class qf_profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 3), ("ms", ctypes.c_double * 3)]
 
 
+QF_LAUNCH_GRAPH, QF_LAUNCH_MERGED, QF_LAUNCH_PER_CIRCUIT = 0, 1, 2
+
+
+class qf_batch_info(ctypes.Structure):
+    _fields_ = [("n_circuits", ctypes.c_int32), ("samples", ctypes.c_int64),
+                ("fwd_steps", ctypes.c_int32), ("bwd_steps", ctypes.c_int32),
+                ("fwd_launches", ctypes.c_int64), ("bwd_launches", ctypes.c_int64),
+                ("fwd_jobs", ctypes.c_int64), ("bwd_jobs", ctypes.c_int64),
+                ("fwd_bytes", ctypes.c_double), ("bwd_bytes", ctypes.c_double),
+                ("fwd_flops", ctypes.c_double), ("bwd_flops", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -82,6 +94,10 @@ def library() -> ctypes.CDLL:
             "qf_forward": [P, P, P, P, P, SZ, P],
             "qf_backward": [P, P, P, P, P, P, P, SZ, P],
             "qf_profile_enable": [P, ctypes.c_int], "qf_profile_read": [P, P],
+            "qf_batch_create": [P, P, I32, P, P], "qf_batch_destroy": [P], "qf_batch_get_info": [P, P],
+            "qf_batch_workspace_size": [P, P], "qf_batch_set_launch_mode": [P, I32],
+            "qf_batch_forward": [P, P, P, P, P, SZ, P],
+            "qf_batch_backward": [P, P, P, P, P, P, P, SZ, P],
         }
         for name, args in sigs.items():
             fn = getattr(lib, name)
@@ -273,3 +289,108 @@ class CircuitFunction(torch.autograd.Function):
 
 def circuit_expectations(theta: torch.Tensor, x: Optional[torch.Tensor], plan: Plan) -> torch.Tensor:
     return CircuitFunction.apply(theta, x, plan)
+
+
+# --------------------------------------------------------------------- mixed batches
+def _ptr_array(ts) -> ctypes.Array:
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def qf_batch_create(circuits, samples, tuning: Optional[qf_tuning]) -> ctypes.c_void_p:
+    n = len(circuits)
+    hs = (ctypes.c_void_p * n)(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in circuits])
+    ss = (ctypes.c_int32 * n)(*[int(v) for v in samples])
+    h = ctypes.c_void_p()
+    _check(library().qf_batch_create(hs, ss, n, ctypes.byref(tuning) if tuning else None, ctypes.byref(h)))
+    return h
+
+
+def qf_batch_destroy(batch) -> None:
+    _check(library().qf_batch_destroy(batch))
+
+
+def qf_batch_get_info(batch) -> qf_batch_info:
+    info = qf_batch_info()
+    _check(library().qf_batch_get_info(batch, ctypes.byref(info)))
+    return info
+
+
+def qf_batch_workspace_size(batch) -> int:
+    n = ctypes.c_size_t()
+    _check(library().qf_batch_workspace_size(batch, ctypes.byref(n)))
+    return int(n.value)
+
+
+def qf_batch_set_launch_mode(batch, mode: int) -> None:
+    _check(library().qf_batch_set_launch_mode(batch, int(mode)))
+
+
+def qf_batch_forward(batch, thetas, xs, Es, ws: torch.Tensor, ws_bytes: int, stream) -> None:
+    _check(library().qf_batch_forward(batch, _ptr_array(thetas), _ptr_array(xs), _ptr_array(Es), _ptr(ws),
+                                      int(ws_bytes), stream))
+
+
+def qf_batch_backward(batch, thetas, xs, dEs, dthetas, dxs, ws: torch.Tensor, ws_bytes: int, stream) -> None:
+    _check(library().qf_batch_backward(batch, _ptr_array(thetas), _ptr_array(xs), _ptr_array(dEs),
+                                       _ptr_array(dthetas), _ptr_array(dxs) if dxs is not None else None, _ptr(ws),
+                                       int(ws_bytes), stream))
+
+
+class Batch:
+    """A qf_batch over several circuits with their own sample counts."""
+
+    def __init__(self, circuits: Sequence[Circuit], samples: Sequence[int], tuning: Optional[qf_tuning] = None,
+                 launch_mode: int = QF_LAUNCH_GRAPH):
+        self.circuits = list(circuits)
+        self.samples = [int(s) for s in samples]
+        if len(self.samples) != len(self.circuits):
+            raise ValueError("one sample count per circuit")
+        self.handle = qf_batch_create([c.handle for c in self.circuits], self.samples, tuning)
+        self.ws_bytes = qf_batch_workspace_size(self.handle)
+        self.set_launch_mode(launch_mode)
+
+    def set_launch_mode(self, mode: int) -> None:
+        qf_batch_set_launch_mode(self.handle, mode)
+
+    @property
+    def info(self) -> qf_batch_info:
+        return qf_batch_get_info(self.handle)
+
+    def new_workspace(self, device=None) -> torch.Tensor:
+        return torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device or "cuda")
+
+    def _check(self, thetas, xs):
+        if len(thetas) != len(self.circuits) or len(xs) != len(self.circuits):
+            raise ValueError("one theta and one x per circuit")
+        for c, s, t, x in zip(self.circuits, self.samples, thetas, xs):
+            if t.dtype != torch.float32 or not t.is_cuda or t.numel() != c.n_params or not t.is_contiguous():
+                raise ValueError("theta: contiguous float32 CUDA tensor of n_params elements per circuit")
+            if c.n_inputs and (x is None or x.dtype != torch.float32 or not x.is_cuda or not x.is_contiguous()
+                               or tuple(x.shape) != (s, c.n_inputs)):
+                raise ValueError("x: contiguous float32 CUDA tensor [samples, n_inputs] per circuit")
+
+    def forward(self, thetas, xs, ws: torch.Tensor):
+        self._check(thetas, xs)
+        Es = [torch.empty(s, c.n_obs, dtype=torch.float32, device=ws.device)
+              for c, s in zip(self.circuits, self.samples)]
+        qf_batch_forward(self.handle, thetas, xs, Es, ws, ws.numel(),
+                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        return Es
+
+    def backward(self, thetas, xs, dEs, ws: torch.Tensor, want_dx: bool = True):
+        self._check(thetas, xs)
+        dEs = [d.contiguous().to(torch.float32) for d in dEs]
+        dthetas = [torch.empty_like(t) for t in thetas]
+        dxs = [torch.empty_like(x) if (want_dx and x is not None) else None for x in xs]
+        qf_batch_backward(self.handle, thetas, xs, dEs, dthetas, dxs, ws, ws.numel(),
+                          ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        return dthetas, dxs
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib is not None:
+            _lib.qf_batch_destroy(h)
+            self.handle = None

@@ -157,18 +157,24 @@ class MixedCircuit:
     x: np.ndarray
 
 
-def c5(n_circuits: int = 256, samples: int = 4, seed: int = 5):
-    """Mixed batch: qubits ~ U{10..18}, layers ~ U{50..500}, RY,RZ + ladder, <Z_0>.
+def mixed(n_circuits: int, qubits=(10, 18), layers=(50, 500), samples: int = 4, seed: int = 5,
+          rotations=("RY", "RZ")):
+    """Mixed batch: qubits ~ U{qubits}, layers ~ U{layers} (inclusive), HEA + ladder, <Z_0>.
 
     Draw order: for the whole set, qubit counts then layer counts; then per
     circuit theta ~ U[0,2pi) and x ~ U[-pi,pi]^(samples x n).
     """
     rng = np.random.default_rng(seed)
-    ns = rng.integers(10, 19, size=n_circuits)
-    ls = rng.integers(50, 501, size=n_circuits)
+    ns = rng.integers(qubits[0], qubits[1] + 1, size=n_circuits)
+    ls = rng.integers(layers[0], layers[1] + 1, size=n_circuits)
     out = []
     for n, L in zip(ns.tolist(), ls.tolist()):
-        theta = rng.uniform(0.0, 2.0 * math.pi, size=2 * n * L).astype(np.float32)
+        theta = rng.uniform(0.0, 2.0 * math.pi, size=len(rotations) * n * L).astype(np.float32)
         x = rng.uniform(-math.pi, math.pi, size=(samples, n)).astype(np.float32)
-        out.append(MixedCircuit(n, L, hea_gates(n, L, ("RY", "RZ")), theta, x))
+        out.append(MixedCircuit(n, L, hea_gates(n, L, rotations), theta, x))
     return out
+
+
+def c5(n_circuits: int = 256, samples: int = 4, seed: int = 5):
+    """256 circuits, qubits ~ U{10..18}, layers ~ U{50..500}, RY,RZ + ladder, 4 samples each, <Z_0>."""
+    return mixed(n_circuits, (10, 18), (50, 500), samples, seed)

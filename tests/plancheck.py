@@ -84,3 +84,39 @@ def stats(n, gates, n_params, n_inputs, zmask, batch, **tuning):
     keys = ["passes", "segments", "ckpt", "micro_batch", "perm", "u2", "cz", "layouts", "runs", "k", "R", "ws_bytes",
             "diag_thread", "diag_amp"]
     return dict(zip(keys, list(out)))
+
+
+def batch_run(circuits, samples, thetas, xs, dEs=None, **tuning):
+    """Mixed batch through the checker.  circuits: (n, gates, n_params, n_inputs, zmask) per circuit.
+
+    Returns (Es, dthetas, dxs, stats)."""
+    n = len(circuits)
+    keep = []
+    descs = (ctypes.c_void_p * n)()
+    for i, (nq, gates, P, F, zm) in enumerate(circuits):
+        d, k = _desc(nq, gates, P, F, zm)
+        keep.append((d, k))
+        descs[i] = ctypes.addressof(d)
+    th = [np.ascontiguousarray(t, dtype=np.float32) for t in thetas]
+    xx = [np.ascontiguousarray(x, dtype=np.float32) for x in xs]
+    Es = [np.zeros((s, len(c[4])), dtype=np.float32) for c, s in zip(circuits, samples)]
+    dth = [np.zeros(len(t), dtype=np.float32) for t in th]
+    dxs = [np.zeros_like(x) for x in xx]
+    dd = None if dEs is None else [np.ascontiguousarray(d, dtype=np.float32) for d in dEs]
+
+    def arr(lst):
+        a = (ctypes.c_void_p * n)()
+        for i, v in enumerate(lst):
+            a[i] = v.ctypes.data if v is not None and v.size else None
+        return a
+
+    t = make_tuning(**tuning)
+    stats = (ctypes.c_int64 * 8)()
+    ss = (ctypes.c_int32 * n)(*[int(s) for s in samples])
+    rc = lib().qfc_batch_run(descs, ss, n, ctypes.byref(t), arr(th), arr(xx), arr(dd) if dd is not None else None,
+                             arr(Es), arr(dth), arr(dxs), stats)
+    if rc != 0:
+        raise RuntimeError(f"qfc_batch_run: {rc} {lib().qfc_last_error().decode()}")
+    keys = ["fwd_steps", "bwd_steps", "fwd_launches", "bwd_launches", "fwd_jobs", "bwd_jobs", "ws_bytes",
+            "max_jobs_per_launch"]
+    return Es, dth, dxs, dict(zip(keys, list(stats)))
