@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--tile-qubits", type=int, default=0)
     ap.add_argument("--reg-qubits", type=int, default=0)
     ap.add_argument("--no-baselines", action="store_true", help="skip the per-gate and CPU baselines")
+    ap.add_argument("--no-autotune", action="store_true", help="ignore the cached autotuned configuration")
     ap.add_argument("--pg-samples", type=int, default=8)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -104,6 +105,15 @@ def main() -> int:
     tun = qfuse.make_tuning(fusion_depth=args.fusion_depth, ckpt_interval=args.ckpt_interval,
                             micro_batch=args.micro_batch, tile_qubits=args.tile_qubits,
                             reg_qubits=args.reg_qubits)
+    tuning_src = "flags" if any((args.fusion_depth, args.ckpt_interval, args.micro_batch, args.tile_qubits,
+                                 args.reg_qubits)) else "default"
+    if tuning_src == "default" and not args.no_autotune:
+        from paper_2603_02804_amd import autotune
+        cached = autotune.cached_tuning(w.n_qubits, w.gates, w.n_obs, B,
+                                        torch.cuda.get_device_name(dev).replace(" ", "_"))
+        if cached:
+            tun = autotune.tuning_from(cached)
+            tuning_src = "autotuned (paper_2603_02804_amd/tuned_configs.json)"
     circ = qfuse.Circuit(w.n_qubits, w.gates, w.n_params, w.n_inputs, w.zmask)
     plan = qfuse.Plan(circ, B, tun)
     info = plan.info
@@ -170,7 +180,7 @@ def main() -> int:
                                f"{w.n_params} angles, RY encoding of 20 features, <Z_0..Z_9> -> 10-class CE",
                    "batch": B, "micro_batch": info.micro_batch, "tile_qubits": info.tile_qubits,
                    "fusion_depth": info.fusion_depth, "fused_passes": info.fused_passes,
-                   "ckpt_interval": info.ckpt_interval, "segments": info.segments},
+                   "ckpt_interval": info.ckpt_interval, "segments": info.segments, "tuning": tuning_src},
         "roofline": roofline,
         "hbm": {"gbs": round(hbm_gbs, 1), "frac": round(hbm_gbs / PEAK_HBM_GBS, 4),
                 "bytes_per_sample": info.fwd_bytes_per_sample + info.bwd_bytes_per_sample},
@@ -293,24 +303,39 @@ def bench_mixed(args, dev) -> int:
         out["merged_eager"] = {"value": round(n_samples / sec_m, 2), "unit": "samples/s"}
         out["per_circuit"] = {"value": round(n_samples / sec_p, 2), "unit": "samples/s",
                               "speedup_graph": round(sec_p / sec, 2)}
-        # CPU oracle: whole circuits in order until the time budget is used, extrapolated by 2^n x gates
+        # CPU oracle on a stratified sample: 8 circuits spread over the cost order, all their
+        # samples, the first layers of each (about cpu_seconds / 8 each), extrapolated in depth
+        # and then by amplitudes x gates x samples to the whole batch
         from oracle.oracle import Oracle
+        from paper_2603_02804_amd.workloads import hea_gates
         orc = Oracle()
-        work_all = sum(float(2 ** c.n_qubits) * len(c.gates) * c.x.shape[0] for c in ws)
-        done_work, spent, items = 0.0, 0.0, 0
-        for c in ws:
-            if spent > args.cpu_seconds:
-                break
+
+        def cost(c):
+            return float(2 ** c.n_qubits) * len(c.gates) * c.x.shape[0]
+
+        order = sorted(range(len(ws)), key=lambda i: cost(ws[i]))
+        pick = [order[int(round(q * (len(order) - 1) / 7))] for q in range(8)]
+        spent, est, cost_pick = 0.0, 0.0, 0.0
+        for i in pick:
+            c = ws[i]
+            n = c.n_qubits
+            t1 = time.perf_counter()
+            g1 = hea_gates(n, 1, ("RY", "RZ"))
+            orc.backward(n, g1, c.theta[:2 * n], c.x, xm, zm, np.ones((c.x.shape[0], 1)))
+            per_layer = max(time.perf_counter() - t1, 1e-4)
+            Lt = int(max(1, min(c.n_layers, round(args.cpu_seconds / 8 / per_layer))))
+            g = hea_gates(n, Lt, ("RY", "RZ"))
             t = time.perf_counter()
-            orc.backward(c.n_qubits, c.gates, c.theta, c.x[:1], xm, zm, np.ones((1, 1)))
-            spent += time.perf_counter() - t
-            done_work += float(2 ** c.n_qubits) * len(c.gates)
-            items += 1
-        per_work = spent / done_work
-        out["cpu_baseline"] = {"value": round(n_samples / (per_work * work_all), 4), "unit": "samples/s",
+            orc.backward(n, g, c.theta[:2 * n * Lt], c.x, xm, zm, np.ones((c.x.shape[0], 1)))
+            dt = time.perf_counter() - t
+            spent += dt + per_layer
+            est += dt * c.n_layers / Lt
+            cost_pick += cost(c)
+        total = est * sum(cost(c) for c in ws) / cost_pick
+        out["cpu_baseline"] = {"value": round(n_samples / total, 4), "unit": "samples/s",
                                "cores": orc.num_threads, "kind": "oracle",
-                               "sample": f"1 sample of each of the first {items} circuits ({spent:.1f} s), "
-                                         f"extrapolated by amplitudes x gates"}
+                               "sample": f"8 circuits spread over the cost order, all 4 samples, leading layers "
+                                         f"({spent:.1f} s), extrapolated in depth and by amplitudes x gates"}
     print(json.dumps(out), flush=True)
     return 0
 

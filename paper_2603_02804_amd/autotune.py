@@ -32,6 +32,7 @@ TUNED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_co
 # (tile qubits, register qubits) shapes with compiled kernels
 TILE_SHAPES = ((12, 4), (13, 5), (11, 4))
 FUSION_DEPTHS = (4, 8, 12, 16)
+MICRO_BATCHES = (8, 16, 32)
 
 
 def paper_memory_bytes(stored_per_layer: float, d: int, b: float, m_sv: int) -> float:
@@ -76,9 +77,16 @@ def cached_tuning(n_qubits, gates, n_obs, batch, device, path: str = TUNED_CACHE
 
 def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequence[int], batch: int,
              budget_bytes: Optional[int] = None, prefix_gates: int = 6000, reps: int = 2,
-             shapes=TILE_SHAPES, depths=FUSION_DEPTHS, cache_path: Optional[str] = None,
-             log=None) -> dict:
-    """Times the candidates on the current GPU and returns the chosen tuning fields."""
+             shapes=TILE_SHAPES, depths=FUSION_DEPTHS, micro_batches=MICRO_BATCHES,
+             cache_path: Optional[str] = None, log=None) -> dict:
+    """Times the candidates on the current GPU and returns the chosen tuning fields.
+
+    Each candidate (tile shape, fusion depth, micro-batch) runs forward + backward
+    of one micro-batch on a prefix of the gate list; the time per sample is scaled
+    by the gate count.  The checkpoint interval then minimises the workspace of
+    the full circuit (memory model above), keeping checkpoints for the whole batch
+    when they fit the budget.
+    """
     import torch
 
     from . import qfuse
@@ -92,45 +100,43 @@ def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequen
     theta = torch.rand(max(P_used, 1), device=dev) * 6.283
     rng = np.random.default_rng(0)
     results = []
+    circ = qfuse.Circuit(n_qubits, pre, max(P_used, 1), n_inputs, z_masks)
     for (k, r) in shapes:
         if k > n_qubits and (k, r) != shapes[0]:
             continue
         for F in depths:
-            tun = qfuse.make_tuning(tile_qubits=k, reg_qubits=r, fusion_depth=F)
-            try:
-                circ = qfuse.Circuit(n_qubits, pre, max(P_used, 1), n_inputs, z_masks)
-                probe = qfuse.Plan(circ, 1, tun)
-                mb = probe.info.micro_batch
-                plan = qfuse.Plan(circ, mb, qfuse.make_tuning(tile_qubits=k, reg_qubits=r, fusion_depth=F,
-                                                              micro_batch=mb))
-            except qfuse.QFuseError:
-                continue
-            x = torch.tensor(rng.uniform(-3.14, 3.14, size=(mb, n_inputs)).astype(np.float32), device=dev) \
-                if n_inputs else None
-            ws = plan.new_workspace(dev)
-            dE = torch.ones(mb, len(z_masks), device=dev)
-            best = float("inf")
-            for _ in range(reps + 1):
-                s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                s0.record()
-                plan.forward(theta, x, ws)
-                plan.backward(theta, x, dE, ws)
-                s1.record()
-                torch.cuda.synchronize()
-                best = min(best, s0.elapsed_time(s1))
-            per_sample_full = best / mb * (G / len(pre))
-            results.append({"tile_qubits": k, "reg_qubits": r, "fusion_depth": F, "micro_batch": mb,
-                            "ms_per_sample": per_sample_full})
-            if log:
-                log(f"autotune k={k} r={r} F={F} mb={mb}: {per_sample_full:.3f} ms/sample")
-            del ws, plan, probe
+            for mb in sorted(set(min(m, batch) for m in micro_batches)):
+                try:
+                    plan = qfuse.Plan(circ, mb, qfuse.make_tuning(tile_qubits=k, reg_qubits=r, fusion_depth=F,
+                                                                  micro_batch=mb))
+                except qfuse.QFuseError:
+                    continue
+                x = torch.tensor(rng.uniform(-3.14, 3.14, size=(mb, n_inputs)).astype(np.float32), device=dev) \
+                    if n_inputs else None
+                ws = plan.new_workspace(dev)
+                dE = torch.ones(mb, len(z_masks), device=dev)
+                best = float("inf")
+                for _ in range(reps + 1):
+                    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    s0.record()
+                    plan.forward(theta, x, ws)
+                    plan.backward(theta, x, dE, ws)
+                    s1.record()
+                    torch.cuda.synchronize()
+                    best = min(best, s0.elapsed_time(s1))
+                per_sample_full = best / mb * (G / len(pre))
+                results.append({"tile_qubits": k, "reg_qubits": r, "fusion_depth": F, "micro_batch": mb,
+                                "ms_per_sample": round(per_sample_full, 4)})
+                if log:
+                    log(f"autotune k={k} r={r} F={F} mb={mb}: {per_sample_full:.3f} ms/sample")
+                del ws, plan
     if not results:
         raise RuntimeError("no candidate tuning could be planned")
     best = min(results, key=lambda d: d["ms_per_sample"])
     out = {k: best[k] for k in ("tile_qubits", "reg_qubits", "fusion_depth", "micro_batch")}
     # checkpoint interval from the memory model of the full circuit
-    circ = qfuse.Circuit(n_qubits, gates, n_params, n_inputs, z_masks)
-    probe = qfuse.Plan(circ, batch, qfuse.make_tuning(tile_qubits=out["tile_qubits"], reg_qubits=out["reg_qubits"],
+    full = qfuse.Circuit(n_qubits, gates, n_params, n_inputs, z_masks)
+    probe = qfuse.Plan(full, batch, qfuse.make_tuning(tile_qubits=out["tile_qubits"], reg_qubits=out["reg_qubits"],
                                                       fusion_depth=out["fusion_depth"],
                                                       micro_batch=out["micro_batch"]))
     passes = probe.info.fused_passes
@@ -143,7 +149,7 @@ def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequen
         store = 0
         c = optimal_ckpt(passes, batch, out["micro_batch"], False)
     out.update({"ckpt_interval": c, "store_ckpt": store, "candidates": results, "device": name,
-                "passes": passes})
+                "passes": passes, "prefix_gates": len(pre)})
     if cache_path:
         cache = _load_cache(cache_path)
         cache[circuit_key(n_qubits, gates, len(z_masks), batch, name)] = out
@@ -157,3 +163,24 @@ def tuning_from(d: dict):
     return qfuse.make_tuning(tile_qubits=d.get("tile_qubits", 0), reg_qubits=d.get("reg_qubits", 0),
                              fusion_depth=d.get("fusion_depth", 0), ckpt_interval=d.get("ckpt_interval", 0),
                              micro_batch=d.get("micro_batch", 0), store_ckpt=d.get("store_ckpt", -1))
+
+
+def main(argv=None) -> int:
+    """Tunes a named workload on the current GPU and writes the cache file."""
+    import argparse
+
+    from .workloads import c2, c3, c4
+
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--workload", default="hea20q1000l", choices=("hea20q1000l", "hea16q200l", "hea12q100l"))
+    ap.add_argument("--out", default=TUNED_CACHE)
+    args = ap.parse_args(argv)
+    w = {"hea20q1000l": c4, "hea16q200l": c3, "hea12q100l": c2}[args.workload]()
+    out = autotune(w.n_qubits, w.gates, w.n_params, w.n_inputs, w.zmask, w.batch, cache_path=args.out,
+                   log=lambda m: print(m, flush=True))
+    print(json.dumps({k: v for k, v in out.items() if k != "candidates"}), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

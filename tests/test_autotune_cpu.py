@@ -1,0 +1,37 @@
+"""Host logic of the autotuner: cache keys and round trip, tuning records, and
+the checkpoint choice against a brute-force minimum of the workspace model."""
+import json
+
+import numpy as np
+
+from paper_2603_02804_amd import autotune
+from paper_2603_02804_amd.workloads import hea_gates
+
+
+def test_cache_roundtrip(tmp_path):
+    g = hea_gates(6, 3, ("RY", "RZ"))
+    key = autotune.circuit_key(6, g, 1, 8, "dev")
+    assert key == autotune.circuit_key(6, g.copy(), 1, 8, "dev")
+    assert key != autotune.circuit_key(6, hea_gates(6, 4, ("RY", "RZ")), 1, 8, "dev")
+    assert key != autotune.circuit_key(6, g, 1, 16, "dev")
+    path = tmp_path / "tuned.json"
+    rec = {"tile_qubits": 12, "reg_qubits": 4, "fusion_depth": 8, "micro_batch": 16, "ckpt_interval": 5,
+           "store_ckpt": 1}
+    path.write_text(json.dumps({key: rec}))
+    assert autotune.cached_tuning(6, g, 1, 8, "dev", path=str(path)) == rec
+    assert autotune.cached_tuning(6, g, 1, 8, "other", path=str(path)) is None
+
+
+def test_tuning_from_fields():
+    t = autotune.tuning_from({"tile_qubits": 11, "reg_qubits": 4, "fusion_depth": 12, "micro_batch": 32,
+                              "ckpt_interval": 7, "store_ckpt": 0})
+    assert (t.mode, t.tile_qubits, t.reg_qubits, t.fusion_depth, t.micro_batch, t.ckpt_interval, t.store_ckpt) == \
+        (0, 11, 4, 12, 32, 7, 0)
+
+
+def test_optimal_ckpt_brute_force():
+    for passes, batch, mb, store in [(249, 1000, 16, True), (249, 1000, 16, False), (40, 64, 8, True),
+                                     (7, 4, 4, True), (1, 1, 1, True)]:
+        c = autotune.optimal_ckpt(passes, batch, mb, store)
+        brute = min(autotune.plan_states(passes, k, batch, mb, store) for k in range(1, passes + 1))
+        assert autotune.plan_states(passes, c, batch, mb, store) == brute
