@@ -21,6 +21,36 @@ __device__ __forceinline__ T cld(const T* p) {
 #endif
 }
 
+// Plan records, read field by field so that every field is a scalar load
+// (whole-struct reads through the constant address space can turn into vector
+// loads followed by a wait on the vector memory counter).
+__device__ __forceinline__ Op ld_op(const Op* p) {
+  Op o;
+  o.kind = cld(&p->kind);
+  o.a = cld(&p->a);
+  o.b = cld(&p->b);
+  o.c = cld(&p->c);
+  o.d = cld(&p->d);
+  o.e = cld(&p->e);
+  o.f = 0;
+  o.g = 0;
+  return o;
+}
+
+__device__ __forceinline__ PhaseEv ld_pev(const PhaseEv* p) {
+  PhaseEv e;
+  e.q = cld(&p->q);
+  e.ref = cld(&p->ref);
+  return e;
+}
+
+__device__ __forceinline__ CzGroup ld_czg(const CzGroup* p) {
+  CzGroup g;
+  g.shift = cld(&p->shift);
+  g.mask = cld(&p->mask);
+  return g;
+}
+
 // Register-bit dispatch: expands STMT with the compile-time bit J == j.
 #define QF_WITH_BIT(R, j, STMT)                      \
   switch (j) {                                       \
@@ -32,13 +62,25 @@ __device__ __forceinline__ T cld(const T* p) {
     default: break;                                  \
   }
 
-__device__ __forceinline__ uint32_t tbase(const uint32_t* tab, int t, int tb) {
-  uint32_t v = 0;
+// Thread part T(t) of a layout index: XOR of tab[i] over the set bits i of the
+// thread id.  The all-ones / all-zero mask of every thread bit is formed once
+// per thread, so that T(t) is one AND-XOR per bit with no branches (the tables
+// hold 0 for bits at or above the tile's thread bits).
+template <int NT>
+struct ThreadBits {
+  static constexpr int B = NT <= 64 ? 6 : NT <= 128 ? 7 : 8;
+  uint32_t m[B];
+  __device__ __forceinline__ explicit ThreadBits(int t) {
 #pragma unroll
-  for (int i = 0; i < kMaxThreadBits; ++i)
-    if (i < tb && ((t >> i) & 1)) v ^= cld(tab + i);
-  return v;
-}
+    for (int i = 0; i < B; ++i) m[i] = 0u - (((uint32_t)t >> i) & 1u);
+  }
+  __device__ __forceinline__ uint32_t operator()(const uint32_t* tab) const {
+    uint32_t v = 0;
+#pragma unroll
+    for (int i = 0; i < B; ++i) v ^= m[i] & cld(tab + i);
+    return v;
+  }
+};
 
 // Per-register-bit contributions of a layout, loaded once per op (uniform).
 template <int R>
@@ -62,16 +104,31 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
 
-// Real rotation [[c, -s], [s, c]] on the pairs along register bit J.
+// Real rotation [[cos f, -sin f], [sin f, cos f]] on the pairs along register
+// bit J, as three shears (x0 -= t x1; x1 += s x0; x0 -= t x1 with t = tan(f/2),
+// s = sin f): three fused multiply-adds per real pair, computed in place.  The
+// run coefficients keep f in [0, pi/2], so |t|, |s| <= 1.
 template <int R, int J>
-__device__ __forceinline__ void apply_ry(float2 (&a)[1 << R], float c, float s) {
+__device__ __forceinline__ void apply_ry(float2 (&a)[1 << R], float t, float s) {
 #pragma unroll
   for (int i = 0; i < (1 << R); ++i) {
     if (i & (1 << J)) continue;
     constexpr int m = 1 << J;
-    const float2 x0 = a[i], x1 = a[i | m];
-    a[i] = make_float2(fmaf(-s, x1.x, c * x0.x), fmaf(-s, x1.y, c * x0.y));
-    a[i | m] = make_float2(fmaf(s, x0.x, c * x1.x), fmaf(s, x0.y, c * x1.y));
+    a[i].x = fmaf(-t, a[i | m].x, a[i].x);
+    a[i].y = fmaf(-t, a[i | m].y, a[i].y);
+    a[i | m].x = fmaf(s, a[i].x, a[i | m].x);
+    a[i | m].y = fmaf(s, a[i].y, a[i | m].y);
+    a[i].x = fmaf(-t, a[i | m].x, a[i].x);
+    a[i].y = fmaf(-t, a[i | m].y, a[i].y);
+  }
+}
+
+// RY on every register bit, bits 0..R-1 in order, straight-line code.
+template <int R, int J = 0>
+__device__ __forceinline__ void apply_ry_all(float2 (&a)[1 << R], const float (&t)[R], const float (&s)[R]) {
+  if constexpr (J < R) {
+    apply_ry<R, J>(a, t[J], s[J]);
+    apply_ry_all<R, J + 1>(a, t, s);
   }
 }
 
@@ -95,6 +152,15 @@ __device__ __forceinline__ void func3(const float2 (&a)[1 << R], const float2 (&
     fx = fmaf(l0.x, p1.y, fx); fx = fmaf(-l0.y, p1.x, fx); fx = fmaf(l1.x, p0.y, fx); fx = fmaf(-l1.y, p0.x, fx);
     fy = fmaf(l1.x, p0.x, fy); fy = fmaf(l1.y, p0.y, fy); fy = fmaf(-l0.x, p1.x, fy); fy = fmaf(-l0.y, p1.y, fy);
     fz = fmaf(l0.x, p0.y, fz); fz = fmaf(-l0.y, p0.x, fz); fz = fmaf(-l1.x, p1.y, fz); fz = fmaf(l1.y, p1.x, fz);
+  }
+}
+
+// Functionals of every register bit, bits 0..R-1 in order, into v[3J..3J+2].
+template <int R, int J = 0>
+__device__ __forceinline__ void func3_all(const float2 (&a)[1 << R], const float2 (&l)[1 << R], float (&v)[16]) {
+  if constexpr (J < R) {
+    func3<R, J>(a, l, v[3 * J], v[3 * J + 1], v[3 * J + 2]);
+    func3_all<R, J + 1>(a, l, v);
   }
 }
 
@@ -164,9 +230,20 @@ __device__ __forceinline__ float2 event_coef(const KArgs& A, int ref, int sample
   return make_float2(cld(p), cld(p + 1));
 }
 
+// LDS amplitude at a byte offset (layouts hold LDS positions in bytes).
+__device__ __forceinline__ float2& lds_at(float2* lds, uint32_t byte_off) {
+  return *reinterpret_cast<float2*>(reinterpret_cast<char*>(lds) + byte_off);
+}
+
 // For register patterns jj in [0, 32): the set of jj with bit j set.
 __device__ __forceinline__ uint32_t bit_pattern(int j) {
   return j == 0 ? 0xAAAAAAAAu : j == 1 ? 0xCCCCCCCCu : j == 2 ? 0xF0F0F0F0u : j == 3 ? 0xFF00FF00u : 0xFFFF0000u;
+}
+
+// Minimum waves per SIMD the pass kernels are compiled for (bounds registers).
+template <int R>
+constexpr int pass_min_waves() {
+  return R <= 4 ? 3 : 1;
 }
 
 template <int R, int NT, bool BWD>
@@ -179,6 +256,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
   const int wave = t >> 6;
   const int tb = A.tb;
   const bool active = t < (1 << tb);
+  const ThreadBits<NT> tbase(t);
   const int sl = item >> A.tiles_log2;
   const int tile = item & ((1 << A.tiles_log2) - 1);
   const int sample = A.sample0 + sl;
@@ -207,14 +285,14 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
   bool pend = false;
 
   // the next op record is fetched while the current one executes
-  Op next = cld(A.ops);
+  Op next = ld_op(A.ops);
   for (int oi = 0; oi < A.n_ops; ++oi) {
     const Op op = next;
-    if (oi + 1 < A.n_ops) next = cld(A.ops + oi + 1);
+    if (oi + 1 < A.n_ops) next = ld_op(A.ops + oi + 1);
     switch (op.kind) {
       case OP_INIT0: {
         const LayoutRec* L = A.layouts + op.a;
-        const uint32_t base = tlog | tbase(L->log_thr, t, tb);
+        const uint32_t base = tlog | tbase(L->log_thr);
         RegBits<R> rb;
         rb.load(L->log_reg);
 #pragma unroll
@@ -224,7 +302,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
       }
       case OP_LOAD: {
         const LayoutRec* L = A.layouts + op.a;
-        const uint32_t base = (op.c ? tout : tin) | tbase(L->mem_thr, t, tb);
+        const uint32_t base = (op.c ? tout : tin) | tbase(L->mem_thr);
         RegBits<R> rb;
         rb.load(L->mem_reg);
         if (active) {
@@ -248,7 +326,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
           pend = false;
         }
         const LayoutRec* L = A.layouts + op.a;
-        const uint32_t base = (op.c ? tout : tin) | tbase(L->mem_thr, t, tb);
+        const uint32_t base = (op.c ? tout : tin) | tbase(L->mem_thr);
         RegBits<R> rb;
         rb.load(L->mem_reg);
         if (active && A.dst) {
@@ -272,38 +350,40 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         }
         const LayoutRec* F = A.layouts + op.a;
         const LayoutRec* T = A.layouts + op.b;
-        const uint32_t bf = tbase(F->lds_thr, t, tb);
-        const uint32_t bt = tbase(T->lds_thr, t, tb);
+        const uint32_t bf = tbase(F->lds_thr);
+        const uint32_t bt = tbase(T->lds_thr);
         RegBits<R> rf, rt;
         rf.load(F->lds_reg);
         rt.load(T->lds_reg);
         if (active) {
 #pragma unroll
-          for (int jj = 0; jj < NA; ++jj) lds[bf ^ rf(jj)] = a[jj];
+          for (int jj = 0; jj < NA; ++jj) lds_at(lds, bf ^ rf(jj)) = a[jj];
         }
         __syncthreads();
         if (active) {
 #pragma unroll
-          for (int jj = 0; jj < NA; ++jj) a[jj] = lds[bt ^ rt(jj)];
+          for (int jj = 0; jj < NA; ++jj) a[jj] = lds_at(lds, bt ^ rt(jj));
         }
         __syncthreads();
         if constexpr (BWD) {
           if (active) {
 #pragma unroll
-            for (int jj = 0; jj < NA; ++jj) lds[bf ^ rf(jj)] = l[jj];
+            for (int jj = 0; jj < NA; ++jj) lds_at(lds, bf ^ rf(jj)) = l[jj];
           }
           __syncthreads();
           if (active) {
 #pragma unroll
-            for (int jj = 0; jj < NA; ++jj) l[jj] = lds[bt ^ rt(jj)];
+            for (int jj = 0; jj < NA; ++jj) l[jj] = lds_at(lds, bt ^ rt(jj));
           }
           __syncthreads();
         }
         break;
       }
       case OP_RY: {
+        // RY(b) as a rotation by f = b/2: shear coefficients tan(f/2), sin f;
+        // the backward un-applies it (f -> -f)
         const float* cp = run_coef(A, op.b, sample);
-        const float c = cld(cp);
+        const float c = BWD ? -cld(cp + 6) : cld(cp + 6);
         const float s = BWD ? -cld(cp + 1) : cld(cp + 1);
         if constexpr (BWD) {
           QF_WITH_BIT(R, op.a, (apply_ry<R, J>(a, c, s), apply_ry<R, J>(l, c, s)));
@@ -312,19 +392,41 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         }
         break;
       }
+      case OP_RYG: {
+        // runs on distinct register bits (mask op.c, entries in bit order); a
+        // bit outside the mask gets t = s = 0, an exact identity, so that the
+        // group is always the same straight-line code
+        const RygEntry* ge = A.rygs + op.b;
+        float t[R], sn[R];
+        int e = 0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+          t[j] = 0.f;
+          sn[j] = 0.f;
+          if ((op.c >> j) & 1) {
+            const float* cp = run_coef(A, cld(&ge[e].ref), sample);
+            t[j] = BWD ? -cld(cp + 6) : cld(cp + 6);
+            sn[j] = BWD ? -cld(cp + 1) : cld(cp + 1);
+            ++e;
+          }
+        }
+        apply_ry_all<R>(a, t, sn);
+        if constexpr (BWD) apply_ry_all<R>(l, t, sn);
+        break;
+      }
       case OP_DIAGT: {
         const LayoutRec* L = A.layouts + op.a;
-        const uint32_t x = tlog | tbase(L->log_thr, t, tb);
+        const uint32_t x = tlog | tbase(L->log_thr);
         uint32_t par = 0;
         for (int i = 0; i < op.c; ++i) {
-          const CzGroup g = cld(A.czg + op.b + i);
+          const CzGroup g = ld_czg(A.czg + op.b + i);
           par ^= x & (x >> g.shift) & g.mask;
         }
         const uint32_t f = (uint32_t)(__popc(par) & 1) << 31;
         ph.x = __uint_as_float(__float_as_uint(ph.x) ^ f);
         ph.y = __uint_as_float(__float_as_uint(ph.y) ^ f);
         for (int i = 0; i < op.e; ++i) {
-          const PhaseEv e = cld(A.pev + op.d + i);
+          const PhaseEv e = ld_pev(A.pev + op.d + i);
           float2 w = event_coef(A, e.ref, sample);
           const bool conj = (((x >> e.q) & 1u) != 0u) != BWD;
           if (conj) w.y = -w.y;
@@ -336,7 +438,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
       case OP_CZA: {
         const CzaRec* C = A.cza + op.a;
         const LayoutRec* L = A.layouts + op.b;
-        const uint32_t x = tlog | tbase(L->log_thr, t, tb);
+        const uint32_t x = tlog | tbase(L->log_thr);
         uint32_t sign = cld(&C->sr);
 #pragma unroll
         for (int j = 0; j < R; ++j)
@@ -346,7 +448,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         break;
       }
       case OP_PHASEA: {
-        const PhaseEv e = cld(A.pev + op.b);
+        const PhaseEv e = ld_pev(A.pev + op.b);
         float2 w = event_coef(A, e.ref, sample);
         if (BWD) w.y = -w.y;
         if constexpr (BWD) {
@@ -360,7 +462,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         if constexpr (!BWD) {
           if (!A.do_expect) break;
           const LayoutRec* L = A.layouts + op.a;
-          const uint32_t base = tlog | tbase(L->log_thr, t, tb);
+          const uint32_t base = tlog | tbase(L->log_thr);
           RegBits<R> rb;
           rb.load(L->log_reg);
           for (int k0 = 0; k0 < A.K; k0 += 16) {
@@ -386,7 +488,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
       case OP_SEED: {
         if constexpr (BWD) {
           const LayoutRec* L = A.layouts + op.a;
-          const uint32_t base = tlog | tbase(L->log_thr, t, tb);
+          const uint32_t base = tlog | tbase(L->log_thr);
           RegBits<R> rb;
           rb.load(L->log_reg);
           const float* g = A.dE + (size_t)sample * A.K;
@@ -413,6 +515,9 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
           float v[16];
 #pragma unroll
           for (int i = 0; i < 16; ++i) v[i] = 0.f;
+          if (op.c) {
+            func3_all<R>(a, l, v);
+          } else {
 #pragma unroll 1
           for (int e = 0; e < m; ++e) {
             float fx = 0.f, fy = 0.f, fz = 0.f;
@@ -426,6 +531,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
                 v[3 * q + 1] = fy;
                 v[3 * q + 2] = fz;
               }
+          }
           }
           const float s = wave_reduce16(v, lane);
           const int idx = (lane >> 2) & 15;
@@ -560,7 +666,7 @@ __device__ inline D2 run_matrix(const Tabs& T, const RunRec& rr, const float* th
   return U;
 }
 
-// Run coefficients.  zyz = 1: [cos(b/2), sin(b/2), u, v] of the RZ RY RZ split;
+// Run coefficients.  zyz = 1: [cos(b/2), sin(b/2), u, v, tan(b/4)] of the RZ RY RZ split;
 // zyz = 0: the 2x2 matrix row-major (one-gate runs of the per-gate baseline).
 __device__ inline void coef_body(const CoefArgs& a, long long idx) {
   if (idx >= a.n_sh + (long long)a.n_ps * a.B) return;
@@ -583,7 +689,8 @@ __device__ inline void coef_body(const CoefArgs& a, long long idx) {
     out[0] = (float)z.cb; out[1] = (float)z.sb;
     out[2] = (float)z.ur; out[3] = (float)z.ui;
     out[4] = (float)z.vr; out[5] = (float)z.vi;
-    out[6] = 0.f; out[7] = 0.f;
+    out[6] = (float)(z.sb / (1.0 + z.cb));   // tan(f/2) of the rotation by f = b/2, f in [0, pi/2]
+    out[7] = 0.f;
   } else {
     for (int i = 0; i < 4; ++i) {
       out[2 * i] = (float)U.r[i];

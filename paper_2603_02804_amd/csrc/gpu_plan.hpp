@@ -54,6 +54,7 @@ inline qf_status upload_plan(const PlanCore& c, DevPlan* d, std::string* msg) {
   push_table(blob, o, c.S.events);       // 20
   push_table(blob, o, c.S.pass_run_begin);  // 21
   push_table(blob, o, c.S.pass_runs);    // 22
+  push_table(blob, o, c.S.rygs);         // 23
   d->bytes = blob.size();
   if (hipMalloc(&d->blob, d->bytes) != hipSuccess) {
     if (msg) *msg = "hipMalloc of plan tables failed";
@@ -90,6 +91,7 @@ inline qf_status upload_plan(const PlanCore& c, DevPlan* d, std::string* msg) {
   t.events = (const EventRec*)(b + o[20]);
   t.pass_run_begin = (const int32_t*)(b + o[21]);
   t.pass_runs = (const int32_t*)(b + o[22]);
+  p.rygs = (const RygEntry*)(b + o[23]);
   return QF_OK;
 }
 

@@ -35,6 +35,7 @@ struct PlanPtrs {
   const LayoutRec* layouts = nullptr;
   const CzGroup* czg = nullptr;
   const FuncEntry* funcs = nullptr;
+  const RygEntry* rygs = nullptr;
   const PassRec* passes = nullptr;
   const uint32_t* zmask = nullptr;
   const PhaseEv* pev = nullptr;
@@ -48,6 +49,7 @@ struct KArgs {
   const LayoutRec* layouts;
   const CzGroup* czg;
   const FuncEntry* funcs;
+  const RygEntry* rygs;
   const PassRec* prec;
   const PhaseEv* pev;
   const CzaRec* cza;
@@ -147,6 +149,7 @@ inline KArgs make_pass_args(const PlanCore& c, const PlanPtrs& d, const CoefPtrs
   A.layouts = d.layouts;
   A.czg = d.czg;
   A.funcs = d.funcs;
+  A.rygs = d.rygs;
   A.prec = d.passes + L.pass;
   A.pev = d.pev;
   A.cza = d.cza;

@@ -150,12 +150,12 @@ LayoutRec make_layout(const std::vector<int>& reg_pos, const std::vector<int>& t
   for (int j = 0; j < kMaxR; ++j) {
     L.reg_qubit[j] = (j < R) ? local[reg_pos[j]] : -1;
     if (j >= R) continue;
-    L.lds_reg[j] = lds_swizzle(1u << reg_pos[j]);
+    L.lds_reg[j] = lds_swizzle(1u << reg_pos[j]) * kLdsElemBytes;
     L.log_reg[j] = 1u << local[reg_pos[j]];
     L.mem_reg[j] = map ? (1u << (*map)[local[reg_pos[j]]]) : 0u;
   }
   for (size_t b = 0; b < thr_pos.size(); ++b) {
-    L.lds_thr[b] = lds_swizzle(1u << thr_pos[b]);
+    L.lds_thr[b] = lds_swizzle(1u << thr_pos[b]) * kLdsElemBytes;
     L.log_thr[b] = 1u << local[thr_pos[b]];
     L.mem_thr[b] = map ? (1u << (*map)[local[thr_pos[b]]]) : 0u;
   }
@@ -183,6 +183,65 @@ std::vector<int> order_thread_positions(std::vector<int> free_pos, int tb) {
 
 void build_gate_runs(const Circuit& c, Schedule* s) {
   build_runs(c, *s, nullptr, nullptr, true);
+}
+
+// Replaces every maximal sequence of consecutive RY ops on distinct register
+// bits by one OP_RYG op (entries sorted by bit: the rotations commute), and marks
+// FUNC ops whose entries are exactly register bits 0..R-1 in order.  The kernels
+// apply a full group in straight-line code.
+static void group_register_runs(Schedule* Sp) {
+  Schedule& S = *Sp;
+  std::vector<Op> out;
+  out.reserve(S.ops.size());
+  auto regroup = [&](int begin, int count, int* nb, int* nc) {
+    *nb = (int)out.size();
+    int i = begin;
+    const int end = begin + count;
+    while (i < end) {
+      const Op& o = S.ops[i];
+      if (o.kind == OP_FUNC) {
+        Op f = o;
+        bool seq = (o.a == S.R);
+        for (int e = 0; e < o.a && seq; ++e) seq = (S.funcs[o.b + e].regbit == e);
+        f.c = seq ? 1 : 0;
+        out.push_back(f);
+        ++i;
+        continue;
+      }
+      if (o.kind != OP_RY) {
+        out.push_back(o);
+        ++i;
+        continue;
+      }
+      int j = i;
+      uint32_t bits = 0;
+      while (j < end && S.ops[j].kind == OP_RY && !((bits >> S.ops[j].a) & 1)) {
+        bits |= 1u << S.ops[j].a;
+        ++j;
+      }
+      if (j - i == 1) {
+        out.push_back(o);
+      } else {
+        std::vector<RygEntry> es;
+        for (int m = i; m < j; ++m) es.push_back({S.ops[m].a, S.ops[m].b});
+        std::sort(es.begin(), es.end(), [](const RygEntry& x, const RygEntry& y) { return x.regbit < y.regbit; });
+        out.push_back({OP_RYG, (int)es.size(), (int)S.rygs.size(), (int)bits, 0, 0, 0, 0});
+        S.rygs.insert(S.rygs.end(), es.begin(), es.end());
+      }
+      i = j;
+    }
+    *nc = (int)out.size() - *nb;
+  };
+  for (PassRec& pr : S.passes) {
+    int b, c;
+    regroup(pr.fop_begin, pr.fop_count, &b, &c);
+    pr.fop_begin = b;
+    pr.fop_count = c;
+    regroup(pr.bop_begin, pr.bop_count, &b, &c);
+    pr.bop_begin = b;
+    pr.bop_count = c;
+  }
+  S.ops.swap(out);
 }
 
 bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string* msg) {
@@ -626,6 +685,7 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
     pr.bop_count = (int)b.size();
     S.ops.insert(S.ops.end(), b.begin(), b.end());
   }
+  group_register_runs(&S);
   if (runs_left != 0) {
     if (msg) *msg = "scheduler left runs unapplied";
     return false;

@@ -50,6 +50,7 @@ struct Schedule {
   std::vector<LayoutRec> layouts;
   std::vector<CzGroup> czg;
   std::vector<FuncEntry> funcs;
+  std::vector<RygEntry> rygs;
   std::vector<EventRec> events;       // phase event coefficient definitions
   int n_ev_shared = 0, n_ev_ps = 0;
   std::vector<PhaseEv> pev;           // phase events referenced by DIAGT / PHASEA ops

@@ -42,7 +42,10 @@ enum OpKind : int32_t {
   OP_PHASEA = 8,  // a=register bit, b=phase event: RZ phase on a register-held qubit
   OP_EXPECT = 9,  // a=layout: Z-string expectations of psi -> partial sums
   OP_SEED = 10,   // a=layout: lambda = 2 sum_k g_k O_k psi
-  OP_FUNC = 11,   // a=entries, b=first FuncEntry: Im<lambda|P_q|psi> for P=X,Y,Z
+  OP_FUNC = 11,   // a=entries, b=first FuncEntry, c=1 when the entries are register bits
+                  // 0..R-1 in order: Im<lambda|P_q|psi> for P=X,Y,Z
+  OP_RYG = 12,    // a=entries, b=first RygEntry, c=mask of their register bits: the RY of
+                  // several runs on distinct register bits (they commute), bits ascending
 };
 
 struct Op {
@@ -77,8 +80,10 @@ struct EventRec {
 // Uniform address data of one layout.  Index of the amplitude held by thread
 // t in register slot jj:  T(t) ^ J(jj), with T(t) = XOR of thr[i] over the set
 // bits i of t and J(jj) = XOR of reg[j] over the set bits j of jj.  Three index
-// spaces: LDS element (XOR-swizzled), logical basis index (qubit q at bit q) and
+// spaces: LDS byte offset (XOR-swizzled element index times kLdsElemBytes, so
+// that the XOR is the address), logical basis index (qubit q at bit q) and
 // memory index (only for load / store layouts).
+constexpr uint32_t kLdsElemBytes = 8;   // one complex64 amplitude
 struct LayoutRec {
   uint32_t lds_reg[kMaxR];
   uint32_t lds_thr[kMaxThreadBits];
@@ -105,6 +110,11 @@ struct CzGroup {
 
 struct FuncEntry {
   int32_t regbit, slot;
+};
+
+// One run of an OP_RYG group: its register bit and coefficient ref.
+struct RygEntry {
+  int32_t regbit, ref;
 };
 
 // Per-pass tile mapping.  Tile id bit i selects the value of the i-th non-local

@@ -148,7 +148,7 @@ struct CpuExec {
       }
       const Split z = split(U);
       const float v[8] = {(float)z.cb, (float)z.sb, (float)z.u.real(), (float)z.u.imag(),
-                          (float)z.v.real(), (float)z.v.imag(), 0.f, 0.f};
+                          (float)z.v.real(), (float)z.v.imag(), (float)(z.sb / (1.0 + z.cb)), 0.f};
       std::memcpy(dst, v, sizeof(v));
     };
     for (size_t i = 0; i < c.coef_runs_sh.size(); ++i) put_run(csh + 8 * i, c.coef_runs_sh[i], 0);
@@ -281,34 +281,53 @@ struct CpuExec {
                 std::vector<char> seen(k_amps, 0);
                 for (int t = 0; t < active; ++t)
                   for (int jj = 0; jj < NA; ++jj) {
-                    uint32_t e = tbase(F.lds_thr, t) ^ reg_index(F.lds_reg, jj);
+                    uint32_t e = (tbase(F.lds_thr, t) ^ reg_index(F.lds_reg, jj)) / kLdsElemBytes;
                     if (e >= k_amps || seen[e]) throw std::runtime_error("LDS layout is not a bijection");
                     seen[e] = 1;
                     lds[e] = v[t * NA + jj];
                   }
                 for (int t = 0; t < active; ++t)
                   for (int jj = 0; jj < NA; ++jj) {
-                    uint32_t e = tbase(T.lds_thr, t) ^ reg_index(T.lds_reg, jj);
+                    uint32_t e = (tbase(T.lds_thr, t) ^ reg_index(T.lds_reg, jj)) / kLdsElemBytes;
                     if (e >= k_amps) oob("LDS read");
                     v[t * NA + jj] = lds[e];
                   }
               }
               break;
             }
-            case OP_RY: {
-              const float* u = coef_row(op.b, sample);
-              const float cc = u[0], ss = L.bwd ? -u[1] : u[1];
-              const int j = op.a;
-              for (int which = 0; which < (L.bwd ? 2 : 1); ++which) {
-                std::vector<CF>& v = which == 0 ? a : l;
-                for (int t = 0; t < active; ++t)
-                  for (int jj = 0; jj < NA; ++jj) {
-                    if ((jj >> j) & 1) continue;
-                    CF x0 = v[t * NA + jj], x1 = v[t * NA + (jj | (1 << j))];
-                    v[t * NA + jj] = CF{cc * x0.re - ss * x1.re, cc * x0.im - ss * x1.im};
-                    v[t * NA + (jj | (1 << j))] = CF{ss * x0.re + cc * x1.re, ss * x0.im + cc * x1.im};
-                  }
+            case OP_RY:
+            case OP_RYG: {
+              const int m = op.kind == OP_RY ? 1 : op.a;
+              uint32_t seen = 0;
+              for (int e = 0; e < m; ++e) {
+                int j = op.a, ref = op.b;
+                if (op.kind == OP_RYG) {
+                  if (op.b + e >= (int)S.rygs.size()) oob("RYG entry");
+                  j = S.rygs[op.b + e].regbit;
+                  ref = S.rygs[op.b + e].ref;
+                  if (j < 0 || j >= R || ((seen >> j) & 1)) oob("RYG register bit");
+                  seen |= 1u << j;
+                }
+                // rotation by f = b/2 as three shears: tan(f/2) and sin f
+                const float* u = coef_row(ref, sample);
+                const float tt = L.bwd ? -u[6] : u[6], ss = L.bwd ? -u[1] : u[1];
+                for (int which = 0; which < (L.bwd ? 2 : 1); ++which) {
+                  std::vector<CF>& v = which == 0 ? a : l;
+                  for (int t = 0; t < active; ++t)
+                    for (int jj = 0; jj < NA; ++jj) {
+                      if ((jj >> j) & 1) continue;
+                      CF& x0 = v[t * NA + jj];
+                      CF& x1 = v[t * NA + (jj | (1 << j))];
+                      x0.re = std::fma(-tt, x1.re, x0.re);
+                      x0.im = std::fma(-tt, x1.im, x0.im);
+                      x1.re = std::fma(ss, x0.re, x1.re);
+                      x1.im = std::fma(ss, x0.im, x1.im);
+                      x0.re = std::fma(-tt, x1.re, x0.re);
+                      x0.im = std::fma(-tt, x1.im, x0.im);
+                    }
+                }
               }
+              if (op.kind == OP_RYG && (int)seen != op.c) oob("RYG bit mask");
               break;
             }
             case OP_DIAGT: {
@@ -697,7 +716,7 @@ int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, i
       cores.push_back(&c);
       PlanPtrs pp;   // host copies of the tables: only their addresses enter the jobs
       pp.ops = c.S.ops.data(); pp.layouts = c.S.layouts.data(); pp.czg = c.S.czg.data();
-      pp.funcs = c.S.funcs.data(); pp.passes = c.S.passes.data(); pp.pev = c.S.pev.data(); pp.cza = c.S.cza.data();
+      pp.funcs = c.S.funcs.data(); pp.rygs = c.S.rygs.data(); pp.passes = c.S.passes.data(); pp.pev = c.S.pev.data(); pp.cza = c.S.cza.data();
       ptrs.push_back(pp);
     }
     std::vector<uint64_t> off;
