@@ -24,9 +24,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "samples/s fwd+adjoint grad (20q×1000L HEA) fused vs per-gate; HBM GB/s % peak"
 PEAK_HBM_GBS = 8000.0
-# FP32 vector peak with the build's instruction set (packed FP32 disabled):
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flops per FMA x 2.4 GHz.
-PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X FP32 vector peak as published: 256 CUs x 128 FP32 FMA lanes per clock
+# (packed FP32) x 2 flops x 2.4 GHz = 157.3 TFLOP/s.  This build disables packed
+# FP32 instructions, which halves the attainable rate (78.6 TFLOP/s); both are
+# reported.
+PEAK_FP32_TFLOPS = 256 * 128 * 2 * 2.4e9 / 1e12
+PEAK_FP32_UNPACKED_TFLOPS = PEAK_FP32_TFLOPS / 2
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bwd_pass_hea20q1000l.json")
 # sources that decide what the pass kernels execute and read/write: when any of
 # them changes, the stored counter measurement no longer applies
@@ -164,6 +167,10 @@ def main() -> int:
         "kernel": f"k_pass<{info.reg_qubits},{info.threads},true> (fused adjoint pass)",
         "bound": "alu", "achieved": round(achieved_tf, 2), "peak": round(PEAK_FP32_TFLOPS, 1), "unit": "TFLOP/s",
         "frac": round(achieved_tf / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+        "peak_unpacked": round(PEAK_FP32_UNPACKED_TFLOPS, 1),
+        "executed_tflops": round(info.exec_bwd_pass_flops_per_sample * B * args.steps / bwd_s / 1e12, 2)
+        if bwd_s > 0 else 0.0,
+        "flops_per_run_amplitude": 48,
         "launches": n_bwd, "avg_launch_ms": round(prof.ms[1] / max(1, n_bwd), 4),
         "flops_per_launch": flops_bwd / max(1, n_bwd), "bytes_per_launch": bytes_bwd / max(1, n_bwd),
         "hbm_gbs": round(bytes_bwd / bwd_s / 1e9, 1) if bwd_s > 0 else 0.0,

@@ -102,11 +102,15 @@ typedef struct {
   int64_t n_perm, n_u2, n_cz; /* ops per sample summed over forward passes            */
   double fwd_bytes_per_sample;   /* algorithmic HBM bytes, forward                    */
   double bwd_bytes_per_sample;   /* algorithmic HBM bytes, backward incl. recompute   */
-  double fwd_flops_per_sample;   /* algorithmic fp32 flops, forward                   */
-  double bwd_flops_per_sample;   /* algorithmic fp32 flops, backward incl. recompute  */
+  double fwd_flops_per_sample;   /* algorithmic flops, forward: 16 per amplitude and
+                                    fused run (one 2x2 complex matrix per run)        */
+  double bwd_flops_per_sample;   /* algorithmic flops, backward incl. recompute: 48 per
+                                    amplitude and run in the adjoint pass             */
   double bwd_pass_bytes_per_sample;  /* bytes of the fused adjoint pass kernel only   */
   double bwd_pass_flops_per_sample;  /* flops of the fused adjoint pass kernel only   */
   int64_t bwd_pass_launches;         /* adjoint pass launches per backward call       */
+  double exec_bwd_pass_flops_per_sample;  /* fp32 flops the adjoint pass kernel executes
+                                             for the rotations and functionals          */
 } qf_plan_info;
 
 typedef struct qf_circuit qf_circuit;

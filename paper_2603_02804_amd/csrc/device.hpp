@@ -100,6 +100,16 @@ struct RegBits {
   }
 };
 
+// a *= b, ordered so that each new component is produced by the last use of
+// the old one (both can then share a register: loop-carried register arrays
+// stay in place instead of being copied every iteration).
+__device__ __forceinline__ void cmul_in(float2& a, float2 b) {
+  const float t1 = a.y * b.y;
+  const float t2 = a.y * b.x;
+  a.y = fmaf(a.x, b.y, t2);
+  a.x = fmaf(a.x, b.x, -t1);
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
@@ -137,7 +147,7 @@ template <int R, int J>
 __device__ __forceinline__ void apply_phase_reg(float2 (&a)[1 << R], float2 w) {
   const float2 wc = make_float2(w.x, -w.y);
 #pragma unroll
-  for (int i = 0; i < (1 << R); ++i) a[i] = cmul(a[i], (i & (1 << J)) ? wc : w);
+  for (int i = 0; i < (1 << R); ++i) cmul_in(a[i], (i & (1 << J)) ? wc : w);
 }
 
 // Im<l|X_q|a>, Im<l|Y_q|a>, Im<l|Z_q|a> over the pairs along register bit J.
@@ -167,16 +177,18 @@ __device__ __forceinline__ void func3_all(const float2 (&a)[1 << R], const float
 template <int NA>
 __device__ __forceinline__ void scale_all(float2 (&a)[NA], float2 p) {
 #pragma unroll
-  for (int i = 0; i < NA; ++i) a[i] = cmul(a[i], p);
+  for (int i = 0; i < NA; ++i) cmul_in(a[i], p);
 }
 
 template <int NA>
 __device__ __forceinline__ void flip_signs(float2 (&a)[NA], uint32_t sign) {
 #pragma unroll
+  // multiplications by +-1 (exact); float arithmetic only, so that the array
+  // never mixes float and integer accesses and stays in registers
   for (int jj = 0; jj < NA; ++jj) {
-    const uint32_t f = (sign << (31 - jj)) & 0x80000000u;
-    a[jj].x = __uint_as_float(__float_as_uint(a[jj].x) ^ f);
-    a[jj].y = __uint_as_float(__float_as_uint(a[jj].y) ^ f);
+    const float g = ((sign >> jj) & 1u) ? -1.f : 1.f;
+    a[jj].x *= g;
+    a[jj].y *= g;
   }
 }
 
@@ -246,6 +258,159 @@ constexpr int pass_min_waves() {
   return R <= 4 ? 3 : 1;
 }
 
+// Per-workgroup context of a fused pass: the uniform launch arguments, the
+// thread's coordinates and the bodies of the ops.  The register arrays and the
+// pending phase are passed by reference, so that they stay in registers.
+template <int R, int NT, bool BWD>
+struct PassCtx {
+  static constexpr int NA = 1 << R;
+  static constexpr int WAVES = NT / 64;
+  KArgs A;
+  float2* lds;
+  ThreadBits<NT> tbase;
+  uint32_t tlog;
+  bool active;
+  int sample, lane, wave, n_slots;
+
+  // op bodies, shared by the single ops and the fused epoch op
+  __device__ __forceinline__ void perm(float2 (&a)[NA], float2 (&l)[NA], float2& ph, int from, int to) const {
+  // flush the pending phase (an exact identity when none is pending)
+  scale_all<NA>(a, ph);
+  if constexpr (BWD) scale_all<NA>(l, ph);
+  ph = make_float2(1.f, 0.f);
+  const LayoutRec* F = A.layouts + from;
+  const LayoutRec* T = A.layouts + to;
+  const uint32_t bf = tbase(F->lds_thr);
+  const uint32_t bt = tbase(T->lds_thr);
+  RegBits<R> rf, rt;
+  rf.load(F->lds_reg);
+  rt.load(T->lds_reg);
+  if (active) {
+#pragma unroll
+    for (int jj = 0; jj < NA; ++jj) lds_at(lds, bf ^ rf(jj)) = a[jj];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int jj = 0; jj < NA; ++jj) a[jj] = lds_at(lds, bt ^ rt(jj));
+  __syncthreads();
+  if constexpr (BWD) {
+    if (active) {
+#pragma unroll
+      for (int jj = 0; jj < NA; ++jj) lds_at(lds, bf ^ rf(jj)) = l[jj];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < NA; ++jj) l[jj] = lds_at(lds, bt ^ rt(jj));
+    __syncthreads();
+  }
+  }
+
+  // RY(b) as a rotation by f = b/2: shear coefficients tan(f/2), sin f; the
+  // backward un-applies it (f -> -f)
+  __device__ __forceinline__ void ry(float2 (&a)[NA], float2 (&l)[NA], float2& ph, int bit, int ref) const {
+    // one run: the group code with identity coefficients on the other bits
+    const float* cp = run_coef(A, ref, sample);
+    const float t0 = BWD ? -cld(cp + 6) : cld(cp + 6);
+    const float s0 = BWD ? -cld(cp + 1) : cld(cp + 1);
+    float tt[R], sn[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      tt[j] = (j == bit) ? t0 : 0.f;
+      sn[j] = (j == bit) ? s0 : 0.f;
+    }
+    apply_ry_all<R>(a, tt, sn);
+    if constexpr (BWD) apply_ry_all<R>(l, tt, sn);
+  }
+  __device__ __forceinline__ void ryg(float2 (&a)[NA], float2 (&l)[NA], float2& ph, int first, int mask) const {
+  const RygEntry* ge = A.rygs + first;
+  float tt[R], sn[R];
+  int e = 0;
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    tt[j] = 0.f;
+    sn[j] = 0.f;
+    if ((mask >> j) & 1) {
+      const float* cp = run_coef(A, cld(&ge[e].ref), sample);
+      tt[j] = BWD ? -cld(cp + 6) : cld(cp + 6);
+      sn[j] = BWD ? -cld(cp + 1) : cld(cp + 1);
+      ++e;
+    }
+  }
+  apply_ry_all<R>(a, tt, sn);
+  if constexpr (BWD) apply_ry_all<R>(l, tt, sn);
+  }
+
+  __device__ __forceinline__ void diagt(float2 (&a)[NA], float2 (&l)[NA], float2& ph, int layout, int czg0, int nczg, int pev0, int npev) const {
+  const LayoutRec* L = A.layouts + layout;
+  const uint32_t x = tlog | tbase(L->log_thr);
+  uint32_t par = 0;
+  for (int i = 0; i < nczg; ++i) {
+    const CzGroup g = ld_czg(A.czg + czg0 + i);
+    par ^= x & (x >> g.shift) & g.mask;
+  }
+  const uint32_t f = (uint32_t)(__popc(par) & 1) << 31;
+  const float g = f ? -1.f : 1.f;
+  ph.x *= g;
+  ph.y *= g;
+  for (int i = 0; i < npev; ++i) {
+    const PhaseEv e = ld_pev(A.pev + pev0 + i);
+    float2 w = event_coef(A, e.ref, sample);
+    const bool conj = (((x >> e.q) & 1u) != 0u) != BWD;
+    if (conj) w.y = -w.y;
+    cmul_in(ph, w);
+  }
+  }
+
+  __device__ __forceinline__ void cza(float2 (&a)[NA], float2 (&l)[NA], float2& ph, int cza, int layout) const {
+  const CzaRec* C = A.cza + cza;
+  const LayoutRec* L = A.layouts + layout;
+  const uint32_t x = tlog | tbase(L->log_thr);
+  uint32_t sign = cld(&C->sr);
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+    if (__popc(x & cld(&C->cmask[j])) & 1) sign ^= bit_pattern(j);
+  flip_signs<NA>(a, sign);
+  if constexpr (BWD) flip_signs<NA>(l, sign);
+  }
+
+  __device__ __forceinline__ void phasea(float2 (&a)[NA], float2 (&l)[NA], float2& ph, int bit, int pev) const {
+    // diag(w, conj w) on register bit `bit`: the factor of slot jj is chosen
+    // with a uniform select, so no code depends on the bit at compile time
+    const PhaseEv e = ld_pev(A.pev + pev);
+    float2 w = event_coef(A, e.ref, sample);
+    if (BWD) w.y = -w.y;
+    const float2 wc = make_float2(w.x, -w.y);
+#pragma unroll
+    for (int jj = 0; jj < NA; ++jj) {
+      const float2 f = ((jj >> bit) & 1) ? wc : w;
+      cmul_in(a[jj], f);
+      if constexpr (BWD) cmul_in(l[jj], f);
+    }
+  }
+  // Im<lambda|P_q|psi> (P = X, Y, Z) of m register bits: wave sums into LDS
+  __device__ __forceinline__ void func(float2 (&a)[NA], float2 (&l)[NA], float2& ph, int m, int first, int) const {
+    if constexpr (BWD) {
+      // functionals of every register bit; entry j (register bit j) names the
+      // run's slot, or -1 when the bit holds no run of this group
+      const FuncEntry* fe = A.funcs + first;
+      float v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = 0.f;
+      func3_all<R>(a, l, v);
+      const float sum = wave_reduce16(v, lane);
+      const int idx = (lane >> 2) & 15;
+      if ((lane & 3) == 0 && idx < 3 * R) {
+        const int e = idx / 3, pq = idx - 3 * e;
+        const int slot = fe[e].slot;
+        if (slot >= 0) {
+          float* part = reinterpret_cast<float*>(lds + A.tile_elems);
+          part[wave * 3 * n_slots + 3 * slot + pq] = sum;
+        }
+      }
+    }
+  }
+};
+
 template <int R, int NT, bool BWD>
 __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
   extern __shared__ float2 lds[];
@@ -282,7 +447,8 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
   // pending per-thread phase of the diagonal gates on thread-held qubits; it
   // multiplies psi (and, in the backward, lambda as well)
   float2 ph = make_float2(1.f, 0.f);
-  bool pend = false;
+
+  const PassCtx<R, NT, BWD> cx{A, lds, tbase, tlog, active, sample, lane, wave, n_slots};
 
   // the next op record is fetched while the current one executes
   Op next = ld_op(A.ops);
@@ -305,26 +471,25 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         const uint32_t base = (op.c ? tout : tin) | tbase(L->mem_thr);
         RegBits<R> rb;
         rb.load(L->mem_reg);
-        if (active) {
-          if (op.b == 0) {
-            const float2* src = reinterpret_cast<const float2*>(A.src0) + (long long)sl * A.s0;
+        // every lane loads: the thread tables are zero above the tile's thread
+        // bits, so lanes beyond the tile read (and later drop) in-tile elements;
+        // an unpredicated load keeps the register arrays in place
+        if (op.b == 0) {
+          const float2* src = reinterpret_cast<const float2*>(A.src0) + (long long)sl * A.s0;
 #pragma unroll
-            for (int jj = 0; jj < NA; ++jj) a[jj] = src[base | rb(jj)];
-          } else if constexpr (BWD) {
-            const float2* src = reinterpret_cast<const float2*>(A.src1) + (long long)sl * A.s1;
+          for (int jj = 0; jj < NA; ++jj) a[jj] = src[base | rb(jj)];
+        } else if constexpr (BWD) {
+          const float2* src = reinterpret_cast<const float2*>(A.src1) + (long long)sl * A.s1;
 #pragma unroll
-            for (int jj = 0; jj < NA; ++jj) l[jj] = src[base | rb(jj)];
-          }
+          for (int jj = 0; jj < NA; ++jj) l[jj] = src[base | rb(jj)];
         }
         break;
       }
       case OP_STORE: {
-        if (pend) {
-          scale_all<NA>(a, ph);
-          if constexpr (BWD) scale_all<NA>(l, ph);
-          ph = make_float2(1.f, 0.f);
-          pend = false;
-        }
+        // flush the pending phase (an exact identity when none is pending)
+        scale_all<NA>(a, ph);
+        if constexpr (BWD) scale_all<NA>(l, ph);
+        ph = make_float2(1.f, 0.f);
         const LayoutRec* L = A.layouts + op.a;
         const uint32_t base = (op.c ? tout : tin) | tbase(L->mem_thr);
         RegBits<R> rb;
@@ -341,120 +506,50 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         }
         break;
       }
-      case OP_PERM: {
-        if (pend) {
-          scale_all<NA>(a, ph);
-          if constexpr (BWD) scale_all<NA>(l, ph);
-          ph = make_float2(1.f, 0.f);
-          pend = false;
-        }
-        const LayoutRec* F = A.layouts + op.a;
-        const LayoutRec* T = A.layouts + op.b;
-        const uint32_t bf = tbase(F->lds_thr);
-        const uint32_t bt = tbase(T->lds_thr);
-        RegBits<R> rf, rt;
-        rf.load(F->lds_reg);
-        rt.load(T->lds_reg);
-        if (active) {
-#pragma unroll
-          for (int jj = 0; jj < NA; ++jj) lds_at(lds, bf ^ rf(jj)) = a[jj];
-        }
-        __syncthreads();
-        if (active) {
-#pragma unroll
-          for (int jj = 0; jj < NA; ++jj) a[jj] = lds_at(lds, bt ^ rt(jj));
-        }
-        __syncthreads();
-        if constexpr (BWD) {
-          if (active) {
-#pragma unroll
-            for (int jj = 0; jj < NA; ++jj) lds_at(lds, bf ^ rf(jj)) = l[jj];
-          }
-          __syncthreads();
-          if (active) {
-#pragma unroll
-            for (int jj = 0; jj < NA; ++jj) l[jj] = lds_at(lds, bt ^ rt(jj));
-          }
-          __syncthreads();
-        }
+      case OP_PERM:
+        cx.perm(a, l, ph, op.a, op.b);
         break;
-      }
-      case OP_RY: {
-        // RY(b) as a rotation by f = b/2: shear coefficients tan(f/2), sin f;
-        // the backward un-applies it (f -> -f)
-        const float* cp = run_coef(A, op.b, sample);
-        const float c = BWD ? -cld(cp + 6) : cld(cp + 6);
-        const float s = BWD ? -cld(cp + 1) : cld(cp + 1);
-        if constexpr (BWD) {
-          QF_WITH_BIT(R, op.a, (apply_ry<R, J>(a, c, s), apply_ry<R, J>(l, c, s)));
+      case OP_RY:
+        cx.ry(a, l, ph, op.a, op.b);
+        break;
+      case OP_RYG:
+        cx.ryg(a, l, ph, op.b, op.c);
+        break;
+      case OP_DIAGT:
+        cx.diagt(a, l, ph, op.a, op.b, op.c, op.d, op.e);
+        break;
+      case OP_CZA:
+        cx.cza(a, l, ph, op.a, op.b);
+        break;
+      case OP_PHASEA:
+        cx.phasea(a, l, ph, op.a, op.b);
+        break;
+      case OP_EPOCH: {
+        // one register epoch in a single loop iteration, sub-steps in program order
+        const EpochRec* E = A.epochs + op.a;
+        const int perm_from = cld(&E->perm_from), perm_to = cld(&E->perm_to);
+        const int diag_layout = cld(&E->diag_layout);
+        const int n_pha = cld(&E->pha_count), pha0 = cld(&E->pha_first);
+        const int cza = cld(&E->cza), cza_layout = cld(&E->cza_layout);
+        const int ry_kind = cld(&E->ry_kind), ry_a = cld(&E->ry_a), ry_b = cld(&E->ry_b);
+        if constexpr (!BWD) {
+          if (perm_from >= 0) cx.perm(a, l, ph, perm_from, perm_to);
+          if (diag_layout >= 0)
+            cx.diagt(a, l, ph, diag_layout, cld(&E->czg_first), cld(&E->czg_count), cld(&E->pev_first), cld(&E->pev_count));
+          for (int i = 0; i < n_pha; ++i) cx.phasea(a, l, ph, cld(&A.phas[pha0 + i].regbit), cld(&A.phas[pha0 + i].pev));
+          if (cza >= 0) cx.cza(a, l, ph, cza, cza_layout);
+          if (ry_kind == 1) cx.ry(a, l, ph, ry_a, ry_b);
+          else if (ry_kind == 2) cx.ryg(a, l, ph, ry_a, ry_b);
         } else {
-          QF_WITH_BIT(R, op.a, (apply_ry<R, J>(a, c, s)));
-        }
-        break;
-      }
-      case OP_RYG: {
-        // runs on distinct register bits (mask op.c, entries in bit order); a
-        // bit outside the mask gets t = s = 0, an exact identity, so that the
-        // group is always the same straight-line code
-        const RygEntry* ge = A.rygs + op.b;
-        float t[R], sn[R];
-        int e = 0;
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-          t[j] = 0.f;
-          sn[j] = 0.f;
-          if ((op.c >> j) & 1) {
-            const float* cp = run_coef(A, cld(&ge[e].ref), sample);
-            t[j] = BWD ? -cld(cp + 6) : cld(cp + 6);
-            sn[j] = BWD ? -cld(cp + 1) : cld(cp + 1);
-            ++e;
-          }
-        }
-        apply_ry_all<R>(a, t, sn);
-        if constexpr (BWD) apply_ry_all<R>(l, t, sn);
-        break;
-      }
-      case OP_DIAGT: {
-        const LayoutRec* L = A.layouts + op.a;
-        const uint32_t x = tlog | tbase(L->log_thr);
-        uint32_t par = 0;
-        for (int i = 0; i < op.c; ++i) {
-          const CzGroup g = ld_czg(A.czg + op.b + i);
-          par ^= x & (x >> g.shift) & g.mask;
-        }
-        const uint32_t f = (uint32_t)(__popc(par) & 1) << 31;
-        ph.x = __uint_as_float(__float_as_uint(ph.x) ^ f);
-        ph.y = __uint_as_float(__float_as_uint(ph.y) ^ f);
-        for (int i = 0; i < op.e; ++i) {
-          const PhaseEv e = ld_pev(A.pev + op.d + i);
-          float2 w = event_coef(A, e.ref, sample);
-          const bool conj = (((x >> e.q) & 1u) != 0u) != BWD;
-          if (conj) w.y = -w.y;
-          ph = cmul(ph, w);
-        }
-        pend = true;
-        break;
-      }
-      case OP_CZA: {
-        const CzaRec* C = A.cza + op.a;
-        const LayoutRec* L = A.layouts + op.b;
-        const uint32_t x = tlog | tbase(L->log_thr);
-        uint32_t sign = cld(&C->sr);
-#pragma unroll
-        for (int j = 0; j < R; ++j)
-          if (__popc(x & cld(&C->cmask[j])) & 1) sign ^= bit_pattern(j);
-        flip_signs<NA>(a, sign);
-        if constexpr (BWD) flip_signs<NA>(l, sign);
-        break;
-      }
-      case OP_PHASEA: {
-        const PhaseEv e = ld_pev(A.pev + op.b);
-        float2 w = event_coef(A, e.ref, sample);
-        if (BWD) w.y = -w.y;
-        if constexpr (BWD) {
-          QF_WITH_BIT(R, op.a, (apply_phase_reg<R, J>(a, w), apply_phase_reg<R, J>(l, w)));
-        } else {
-          QF_WITH_BIT(R, op.a, (apply_phase_reg<R, J>(a, w)));
+          const int n_func = cld(&E->func_count);
+          if (n_func > 0) cx.func(a, l, ph, n_func, cld(&E->func_first), cld(&E->func_full));
+          if (ry_kind == 1) cx.ry(a, l, ph, ry_a, ry_b);
+          else if (ry_kind == 2) cx.ryg(a, l, ph, ry_a, ry_b);
+          if (cza >= 0) cx.cza(a, l, ph, cza, cza_layout);
+          for (int i = 0; i < n_pha; ++i) cx.phasea(a, l, ph, cld(&A.phas[pha0 + i].regbit), cld(&A.phas[pha0 + i].pev));
+          if (diag_layout >= 0)
+            cx.diagt(a, l, ph, diag_layout, cld(&E->czg_first), cld(&E->czg_count), cld(&E->pev_first), cld(&E->pev_count));
+          if (perm_from >= 0) cx.perm(a, l, ph, perm_from, perm_to);
         }
         break;
       }
@@ -508,41 +603,9 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         }
         break;
       }
-      case OP_FUNC: {
-        if constexpr (BWD) {
-          const FuncEntry* fe = A.funcs + op.b;
-          const int m = op.a;
-          float v[16];
-#pragma unroll
-          for (int i = 0; i < 16; ++i) v[i] = 0.f;
-          if (op.c) {
-            func3_all<R>(a, l, v);
-          } else {
-#pragma unroll 1
-          for (int e = 0; e < m; ++e) {
-            float fx = 0.f, fy = 0.f, fz = 0.f;
-            const int rb = cld(&fe[e].regbit);
-            QF_WITH_BIT(R, rb, (func3<R, J>(a, l, fx, fy, fz)));
-            // place the three sums of entry e (static register indices)
-#pragma unroll
-            for (int q = 0; q < R; ++q)
-              if (q == e) {
-                v[3 * q] = fx;
-                v[3 * q + 1] = fy;
-                v[3 * q + 2] = fz;
-              }
-          }
-          }
-          const float s = wave_reduce16(v, lane);
-          const int idx = (lane >> 2) & 15;
-          if ((lane & 3) == 0 && idx < 3 * m) {
-            const int e = idx / 3, pq = idx - 3 * e;
-            float* part = reinterpret_cast<float*>(lds + A.tile_elems);
-            part[wave * 3 * n_slots + 3 * fe[e].slot + pq] = s;
-          }
-        }
+      case OP_FUNC:
+        cx.func(a, l, ph, op.a, op.b, op.c);
         break;
-      }
       default:
         break;
     }

@@ -55,6 +55,8 @@ inline qf_status upload_plan(const PlanCore& c, DevPlan* d, std::string* msg) {
   push_table(blob, o, c.S.pass_run_begin);  // 21
   push_table(blob, o, c.S.pass_runs);    // 22
   push_table(blob, o, c.S.rygs);         // 23
+  push_table(blob, o, c.S.epochs);       // 24
+  push_table(blob, o, c.S.phas);         // 25
   d->bytes = blob.size();
   if (hipMalloc(&d->blob, d->bytes) != hipSuccess) {
     if (msg) *msg = "hipMalloc of plan tables failed";
@@ -92,6 +94,8 @@ inline qf_status upload_plan(const PlanCore& c, DevPlan* d, std::string* msg) {
   t.pass_run_begin = (const int32_t*)(b + o[21]);
   t.pass_runs = (const int32_t*)(b + o[22]);
   p.rygs = (const RygEntry*)(b + o[23]);
+  p.epochs = (const EpochRec*)(b + o[24]);
+  p.phas = (const PhaEntry*)(b + o[25]);
   return QF_OK;
 }
 

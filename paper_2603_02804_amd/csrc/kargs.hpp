@@ -36,6 +36,8 @@ struct PlanPtrs {
   const CzGroup* czg = nullptr;
   const FuncEntry* funcs = nullptr;
   const RygEntry* rygs = nullptr;
+  const EpochRec* epochs = nullptr;
+  const PhaEntry* phas = nullptr;
   const PassRec* passes = nullptr;
   const uint32_t* zmask = nullptr;
   const PhaseEv* pev = nullptr;
@@ -50,6 +52,8 @@ struct KArgs {
   const CzGroup* czg;
   const FuncEntry* funcs;
   const RygEntry* rygs;
+  const EpochRec* epochs;
+  const PhaEntry* phas;
   const PassRec* prec;
   const PhaseEv* pev;
   const CzaRec* cza;
@@ -150,6 +154,8 @@ inline KArgs make_pass_args(const PlanCore& c, const PlanPtrs& d, const CoefPtrs
   A.czg = d.czg;
   A.funcs = d.funcs;
   A.rygs = d.rygs;
+  A.epochs = d.epochs;
+  A.phas = d.phas;
   A.prec = d.passes + L.pass;
   A.pev = d.pev;
   A.cza = d.cza;

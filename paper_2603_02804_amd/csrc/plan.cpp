@@ -199,15 +199,6 @@ static void group_register_runs(Schedule* Sp) {
     const int end = begin + count;
     while (i < end) {
       const Op& o = S.ops[i];
-      if (o.kind == OP_FUNC) {
-        Op f = o;
-        bool seq = (o.a == S.R);
-        for (int e = 0; e < o.a && seq; ++e) seq = (S.funcs[o.b + e].regbit == e);
-        f.c = seq ? 1 : 0;
-        out.push_back(f);
-        ++i;
-        continue;
-      }
       if (o.kind != OP_RY) {
         out.push_back(o);
         ++i;
@@ -238,6 +229,94 @@ static void group_register_runs(Schedule* Sp) {
     pr.fop_begin = b;
     pr.fop_count = c;
     regroup(pr.bop_begin, pr.bop_count, &b, &c);
+    pr.bop_begin = b;
+    pr.bop_count = c;
+  }
+  S.ops.swap(out);
+}
+
+// Folds each register epoch into one OP_EPOCH op.  Forward: a PERM, then
+// optionally a DIAGT, PHASEA ops, a CZA and one RY / RYG, in that order.
+// Backward: optionally a FUNC, one RY / RYG, a CZA, PHASEA ops and a DIAGT,
+// ending with a PERM.  The sub-ops keep their order, so execution is unchanged;
+// ops outside these patterns stay as they are.
+static void fuse_epochs(Schedule* Sp) {
+  Schedule& S = *Sp;
+  std::vector<Op> out;
+  out.reserve(S.ops.size());
+  auto blank = []() {
+    EpochRec e;
+    std::memset(&e, 0, sizeof(e));
+    e.perm_from = e.perm_to = e.diag_layout = e.cza = -1;
+    return e;
+  };
+  auto take_ry = [&](const Op& o, EpochRec* e) {
+    if (o.kind == OP_RY) { e->ry_kind = 1; e->ry_a = o.a; e->ry_b = o.b; }
+    else { e->ry_kind = 2; e->ry_a = o.b; e->ry_b = o.c; }
+  };
+  auto take_phas = [&](int* j, int end, EpochRec* e) {
+    e->pha_first = (int)S.phas.size();
+    while (*j < end && S.ops[*j].kind == OP_PHASEA) {
+      S.phas.push_back({S.ops[*j].a, S.ops[*j].b});
+      ++*j;
+    }
+    e->pha_count = (int)S.phas.size() - e->pha_first;
+  };
+  auto take_diag = [&](const Op& o, EpochRec* e) {
+    e->diag_layout = o.a; e->czg_first = o.b; e->czg_count = o.c; e->pev_first = o.d; e->pev_count = o.e;
+  };
+  auto emit = [&](const EpochRec& e) {
+    out.push_back({OP_EPOCH, (int)S.epochs.size(), 0, 0, 0, 0, 0, 0});
+    S.epochs.push_back(e);
+  };
+  auto fwd = [&](int begin, int count, int* nb, int* nc) {
+    *nb = (int)out.size();
+    const int end = begin + count;
+    int i = begin;
+    while (i < end) {
+      if (S.ops[i].kind != OP_PERM) { out.push_back(S.ops[i++]); continue; }
+      EpochRec e = blank();
+      e.perm_from = S.ops[i].a;
+      e.perm_to = S.ops[i].b;
+      int j = i + 1;
+      if (j < end && S.ops[j].kind == OP_DIAGT) take_diag(S.ops[j++], &e);
+      take_phas(&j, end, &e);
+      if (j < end && S.ops[j].kind == OP_CZA) { e.cza = S.ops[j].a; e.cza_layout = S.ops[j].b; ++j; }
+      if (j < end && (S.ops[j].kind == OP_RY || S.ops[j].kind == OP_RYG)) take_ry(S.ops[j++], &e);
+      emit(e);
+      i = j;
+    }
+    *nc = (int)out.size() - *nb;
+  };
+  auto bwd = [&](int begin, int count, int* nb, int* nc) {
+    *nb = (int)out.size();
+    const int end = begin + count;
+    int i = begin;
+    while (i < end) {
+      const int k = S.ops[i].kind;
+      if (k != OP_FUNC && k != OP_RY && k != OP_RYG) { out.push_back(S.ops[i++]); continue; }
+      EpochRec e = blank();
+      int j = i;
+      if (S.ops[j].kind == OP_FUNC) {
+        e.func_count = S.ops[j].a; e.func_first = S.ops[j].b; e.func_full = S.ops[j].c;
+        ++j;
+      }
+      if (j < end && (S.ops[j].kind == OP_RY || S.ops[j].kind == OP_RYG)) take_ry(S.ops[j++], &e);
+      if (j < end && S.ops[j].kind == OP_CZA) { e.cza = S.ops[j].a; e.cza_layout = S.ops[j].b; ++j; }
+      take_phas(&j, end, &e);
+      if (j < end && S.ops[j].kind == OP_DIAGT) take_diag(S.ops[j++], &e);
+      if (j < end && S.ops[j].kind == OP_PERM) { e.perm_from = S.ops[j].a; e.perm_to = S.ops[j].b; ++j; }
+      emit(e);
+      i = j;
+    }
+    *nc = (int)out.size() - *nb;
+  };
+  for (PassRec& pr : S.passes) {
+    int b, c;
+    fwd(pr.fop_begin, pr.fop_count, &b, &c);
+    pr.fop_begin = b;
+    pr.fop_count = c;
+    bwd(pr.bop_begin, pr.bop_count, &b, &c);
     pr.bop_begin = b;
     pr.bop_count = c;
   }
@@ -670,8 +749,10 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
           bits |= 1u << f[j].a;
         }
         int fb = (int)S.funcs.size();
-        for (int m = j; m <= i; ++m) S.funcs.push_back({f[m].a, S.runs[f[m].c].slot});
-        b.push_back({OP_FUNC, i - j + 1, fb, 0, 0, 0, 0, 0});
+        // one entry per register bit, indexed by the bit; slot -1: no run there
+        for (int q = 0; q < R; ++q) S.funcs.push_back({q, -1});
+        for (int m = j; m <= i; ++m) S.funcs[fb + f[m].a].slot = S.runs[f[m].c].slot;
+        b.push_back({OP_FUNC, R, fb, 0, 0, 0, 0, 0});
         for (int m = i; m >= j; --m) b.push_back(f[m]);
         i = j - 1;
         continue;
@@ -686,6 +767,7 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
     S.ops.insert(S.ops.end(), b.begin(), b.end());
   }
   group_register_runs(&S);
+  fuse_epochs(&S);
   if (runs_left != 0) {
     if (msg) *msg = "scheduler left runs unapplied";
     return false;

@@ -51,6 +51,8 @@ struct Schedule {
   std::vector<CzGroup> czg;
   std::vector<FuncEntry> funcs;
   std::vector<RygEntry> rygs;
+  std::vector<EpochRec> epochs;
+  std::vector<PhaEntry> phas;
   std::vector<EventRec> events;       // phase event coefficient definitions
   int n_ev_shared = 0, n_ev_ps = 0;
   std::vector<PhaseEv> pev;           // phase events referenced by DIAGT / PHASEA ops

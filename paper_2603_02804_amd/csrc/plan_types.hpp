@@ -42,10 +42,12 @@ enum OpKind : int32_t {
   OP_PHASEA = 8,  // a=register bit, b=phase event: RZ phase on a register-held qubit
   OP_EXPECT = 9,  // a=layout: Z-string expectations of psi -> partial sums
   OP_SEED = 10,   // a=layout: lambda = 2 sum_k g_k O_k psi
-  OP_FUNC = 11,   // a=entries, b=first FuncEntry, c=1 when the entries are register bits
-                  // 0..R-1 in order: Im<lambda|P_q|psi> for P=X,Y,Z
+  OP_FUNC = 11,   // a=R entries, b=first FuncEntry (entry j: register bit j, slot or -1):
+                  // Im<lambda|P_q|psi> for P=X,Y,Z
   OP_RYG = 12,    // a=entries, b=first RygEntry, c=mask of their register bits: the RY of
                   // several runs on distinct register bits (they commute), bits ascending
+  OP_EPOCH = 13,  // a=EpochRec: one register epoch (PERM, DIAGT, PHASEA*, CZA, RY/RYG forward;
+                  // FUNC, RY/RYG, CZA, PHASEA*, DIAGT, PERM backward) in one loop iteration
 };
 
 struct Op {
@@ -115,6 +117,22 @@ struct FuncEntry {
 // One run of an OP_RYG group: its register bit and coefficient ref.
 struct RygEntry {
   int32_t regbit, ref;
+};
+
+// PHASEA inside an epoch: register bit and phase event.
+struct PhaEntry {
+  int32_t regbit, pev;
+};
+
+// The sub-ops of one epoch; -1 / 0 fields mark sub-ops that are absent.
+struct EpochRec {
+  int32_t perm_from, perm_to;                          // PERM (from -1: none)
+  int32_t diag_layout, czg_first, czg_count, pev_first, pev_count;   // DIAGT (layout -1: none)
+  int32_t pha_first, pha_count;                        // PhaEntry range
+  int32_t cza, cza_layout;                             // CZA (-1: none)
+  int32_t ry_kind, ry_a, ry_b;                         // 0 none; 1 RY(bit a, ref b); 2 RYG(first a, mask b)
+  int32_t func_count, func_first, func_full;           // FUNC (backward; func_full unused)
+  int32_t pad;
 };
 
 // Per-pass tile mapping.  Tile id bit i selects the value of the i-th non-local

@@ -228,7 +228,8 @@ struct CpuExec {
         };
         const int64_t item = (int64_t)sl * tiles + tile;
         for (int oi = 0; oi < nops; ++oi) {
-          const Op& op = S.ops[b0 + oi];
+          const std::vector<Op> seq = expand_op(S.ops[b0 + oi], L.bwd);
+          for (const Op& op : seq) {
           switch (op.kind) {
             case OP_INIT0: {
               const LayoutRec& Ly = S.layouts[op.a];
@@ -420,6 +421,7 @@ struct CpuExec {
               const int ns = pr.n_slots;
               for (int e = 0; e < op.a; ++e) {
                 const FuncEntry& fe = S.funcs[op.b + e];
+                if (fe.slot < 0) continue;   // register bit without a run of this group
                 const int j = fe.regbit;
                 float fw[3] = {0, 0, 0};
                 for (int w = 0; w < waves; ++w) {
@@ -450,9 +452,39 @@ struct CpuExec {
             default:
               throw std::runtime_error("unknown op");
           }
+          }
         }
       }
     }
+  }
+
+  // An epoch op as its sub-ops in execution order; any other op as itself.
+  std::vector<Op> expand_op(const Op& o, bool bwd) const {
+    if (o.kind != OP_EPOCH) return {o};
+    const Schedule& S = c.S;
+    if (o.a < 0 || o.a >= (int)S.epochs.size()) oob("epoch record");
+    const EpochRec& e = S.epochs[o.a];
+    std::vector<Op> perm, diag, pha, cza, ry, func;
+    if (e.perm_from >= 0) perm.push_back({OP_PERM, e.perm_from, e.perm_to, 0, 0, 0, 0, 0});
+    if (e.diag_layout >= 0)
+      diag.push_back({OP_DIAGT, e.diag_layout, e.czg_first, e.czg_count, e.pev_first, e.pev_count, 0, 0});
+    for (int i = 0; i < e.pha_count; ++i) {
+      if (e.pha_first + i >= (int)S.phas.size()) oob("epoch PHASEA entry");
+      pha.push_back({OP_PHASEA, S.phas[e.pha_first + i].regbit, S.phas[e.pha_first + i].pev, 0, 0, 0, 0, 0});
+    }
+    if (e.cza >= 0) cza.push_back({OP_CZA, e.cza, e.cza_layout, 0, 0, 0, 0, 0});
+    if (e.ry_kind == 1) ry.push_back({OP_RY, e.ry_a, e.ry_b, 0, 0, 0, 0, 0});
+    if (e.ry_kind == 2) {
+      int cnt = 0;
+      for (int j = 0; j < 32; ++j) cnt += (e.ry_b >> j) & 1;
+      ry.push_back({OP_RYG, cnt, e.ry_a, e.ry_b, 0, 0, 0, 0});
+    }
+    if (e.func_count > 0) func.push_back({OP_FUNC, e.func_count, e.func_first, e.func_full, 0, 0, 0, 0});
+    std::vector<Op> out;
+    auto add = [&](const std::vector<Op>& v) { out.insert(out.end(), v.begin(), v.end()); };
+    if (!bwd) { add(perm); add(diag); add(pha); add(cza); add(ry); }
+    else { add(func); add(ry); add(cza); add(pha); add(diag); add(perm); }
+    return out;
   }
 
   void reduce_E(int nb, int sample0, const float* partE, float* E) {
@@ -716,7 +748,7 @@ int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, i
       cores.push_back(&c);
       PlanPtrs pp;   // host copies of the tables: only their addresses enter the jobs
       pp.ops = c.S.ops.data(); pp.layouts = c.S.layouts.data(); pp.czg = c.S.czg.data();
-      pp.funcs = c.S.funcs.data(); pp.rygs = c.S.rygs.data(); pp.passes = c.S.passes.data(); pp.pev = c.S.pev.data(); pp.cza = c.S.cza.data();
+      pp.funcs = c.S.funcs.data(); pp.rygs = c.S.rygs.data(); pp.epochs = c.S.epochs.data(); pp.phas = c.S.phas.data(); pp.passes = c.S.passes.data(); pp.pev = c.S.pev.data(); pp.cza = c.S.cza.data();
       ptrs.push_back(pp);
     }
     std::vector<uint64_t> off;

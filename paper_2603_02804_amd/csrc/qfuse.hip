@@ -552,21 +552,25 @@ qf_status qf_plan_get_info(const qf_plan* p, qf_plan_info* info) {
   const double adj = 3 * P - 2;   // the seed pass reads no lambda, pass 0 writes none
   info->bwd_pass_bytes_per_sample = adj * SB;
   info->bwd_bytes_per_sample = (recompute + adj) * SB + (c.store ? 0 : info->fwd_bytes_per_sample);
-  // algorithmic flops of a run: its real RY on every complex amplitude pair is 8
-  // multiply-adds per pair (8 flops per amplitude); the adjoint applies RY^dagger
-  // to psi and lambda (16 flops per amplitude) and evaluates the three
-  // functionals (6 multiply-adds, 12 flops per amplitude)
+  // algorithmic flops of a run, per amplitude, in the method's terms (one
+  // fused 2x2 complex matrix per run): forward and recompute apply it (8
+  // multiply-adds, 16 flops); the adjoint pass un-applies it from psi and
+  // lambda and forms the gradient inner products (about 24 multiply-adds, 48
+  // flops).  The kernels execute fewer: the run is a real RY between diagonal
+  // phases, applied as three shears (6 flops per amplitude), so the adjoint pass
+  // executes 2 x 6 + 12 (three functionals) = 24 flops per amplitude and run.
   const double runs = (double)S.n_u2;
-  info->fwd_flops_per_sample = runs * 8 * A;
+  info->fwd_flops_per_sample = runs * 16 * A;
   double rec_runs = 0;
   for (int s = 0; s < c.n_seg; ++s)
     for (int q = c.seg_begin[s]; q <= c.seg_begin[s + 1] - 2; ++q) {
       const PassRec& pr = S.passes[q];
       rec_runs += pr.n_slots;
     }
-  info->bwd_pass_flops_per_sample = runs * 28 * A;
-  info->bwd_flops_per_sample = info->bwd_pass_flops_per_sample + rec_runs * 8 * A +
+  info->bwd_pass_flops_per_sample = runs * 48 * A;
+  info->bwd_flops_per_sample = info->bwd_pass_flops_per_sample + rec_runs * 16 * A +
                                (c.store ? 0 : info->fwd_flops_per_sample);
+  info->exec_bwd_pass_flops_per_sample = runs * 24 * A;
   info->bwd_pass_launches = (int64_t)c.P * ((c.B + c.mb - 1) / c.mb);
   return QF_OK;
 }

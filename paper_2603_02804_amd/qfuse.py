@@ -57,7 +57,7 @@ class qf_plan_info(ctypes.Structure):
                 + [(n, ctypes.c_double) for n in ("fwd_bytes_per_sample", "bwd_bytes_per_sample",
                                                   "fwd_flops_per_sample", "bwd_flops_per_sample",
                                                   "bwd_pass_bytes_per_sample", "bwd_pass_flops_per_sample")]
-                + [("bwd_pass_launches", ctypes.c_int64)])
+                + [("bwd_pass_launches", ctypes.c_int64), ("exec_bwd_pass_flops_per_sample", ctypes.c_double)])
 
 
 class qf_profile(ctypes.Structure):
