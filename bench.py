@@ -158,8 +158,8 @@ def main() -> int:
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        shape = {k: getattr(info, k) for k in ("tile_qubits", "reg_qubits", "fusion_depth", "fused_passes",
-                                               "micro_batch")}
+        # per-sample bytes depend on the pass structure, not on how samples are grouped into micro-batches
+        shape = {k: getattr(info, k) for k in ("tile_qubits", "reg_qubits", "fusion_depth", "fused_passes")}
         if tr.get("kernel_src_sha") == kernel_sha() and tr.get("plan") == shape and not args.layers:
             # counters were taken per sample over every adjoint pass launch
             traffic = round(tr["hbm_bytes_per_sample"] * B * args.steps / max(1, n_bwd))
@@ -186,7 +186,7 @@ def main() -> int:
         "config": {"workload": f"hea20q{w.n_layers}l: 20-qubit HEA, {w.n_layers} layers of RX,RY,RZ + CZ ladder, "
                                f"{w.n_params} angles, RY encoding of 20 features, <Z_0..Z_9> -> 10-class CE",
                    "batch": B, "micro_batch": info.micro_batch, "tile_qubits": info.tile_qubits,
-                   "fusion_depth": info.fusion_depth, "fused_passes": info.fused_passes,
+                   "reg_qubits": info.reg_qubits, "fusion_depth": info.fusion_depth, "fused_passes": info.fused_passes,
                    "ckpt_interval": info.ckpt_interval, "segments": info.segments, "tuning": tuning_src},
         "roofline": roofline,
         "hbm": {"gbs": round(hbm_gbs, 1), "frac": round(hbm_gbs / PEAK_HBM_GBS, 4),

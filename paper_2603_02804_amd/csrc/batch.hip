@@ -42,7 +42,7 @@ __device__ __forceinline__ T* rebase(T* p, char* ws) {
 }
 
 template <int R, int NT, bool BWD>
-__global__ __launch_bounds__(NT, pass_min_waves<R>()) void k_pass_multi(const PassJob* jobs, const int32_t* start, int n_jobs,
+__global__ __launch_bounds__(NT, (pass_min_waves<R, BWD>())) void k_pass_multi(const PassJob* jobs, const int32_t* start, int n_jobs,
                                                    char* ws, const CircPtrs* ptrs) {
   const int j = find_job(start, n_jobs);
   KArgs A = cld(&jobs[j].A);

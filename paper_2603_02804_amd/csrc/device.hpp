@@ -253,7 +253,7 @@ __device__ __forceinline__ uint32_t bit_pattern(int j) {
 }
 
 // Minimum waves per SIMD the pass kernels are compiled for (bounds registers).
-template <int R>
+template <int R, bool BWD>
 constexpr int pass_min_waves() {
   return R <= 4 ? 3 : 1;
 }
@@ -267,6 +267,7 @@ struct PassCtx {
   static constexpr int WAVES = NT / 64;
   KArgs A;
   float2* lds;
+  float* part;
   ThreadBits<NT> tbase;
   uint32_t tlog;
   bool active;
@@ -397,13 +398,17 @@ struct PassCtx {
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = 0.f;
       func3_all<R>(a, l, v);
+      // lanes beyond a small tile hold copies of in-tile elements: no share
+      if (!active) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = 0.f;
+      }
       const float sum = wave_reduce16(v, lane);
       const int idx = (lane >> 2) & 15;
       if ((lane & 3) == 0 && idx < 3 * R) {
         const int e = idx / 3, pq = idx - 3 * e;
         const int slot = fe[e].slot;
         if (slot >= 0) {
-          float* part = reinterpret_cast<float*>(lds + A.tile_elems);
           part[wave * 3 * n_slots + 3 * slot + pq] = sum;
         }
       }
@@ -413,7 +418,10 @@ struct PassCtx {
 
 template <int R, int NT, bool BWD>
 __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
-  extern __shared__ float2 lds[];
+  // the tile: a static array, so that its base folds into the LDS offsets
+  __shared__ float2 lds[(1 << R) * NT];
+  // backward: per-wave functional partial sums (dynamic size)
+  extern __shared__ float lds_part[];
   constexpr int NA = 1 << R;
   constexpr int WAVES = NT / 64;
   const int t = threadIdx.x;
@@ -448,7 +456,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
   // multiplies psi (and, in the backward, lambda as well)
   float2 ph = make_float2(1.f, 0.f);
 
-  const PassCtx<R, NT, BWD> cx{A, lds, tbase, tlog, active, sample, lane, wave, n_slots};
+  const PassCtx<R, NT, BWD> cx{A, lds, lds_part, tbase, tlog, active, sample, lane, wave, n_slots};
 
   // the next op record is fetched while the current one executes
   Op next = ld_op(A.ops);
@@ -525,31 +533,35 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         cx.phasea(a, l, ph, op.a, op.b);
         break;
       case OP_EPOCH: {
-        // one register epoch in a single loop iteration, sub-steps in program order
-        const EpochRec* E = A.epochs + op.a;
-        const int perm_from = cld(&E->perm_from), perm_to = cld(&E->perm_to);
-        const int diag_layout = cld(&E->diag_layout);
-        const int n_pha = cld(&E->pha_count), pha0 = cld(&E->pha_first);
-        const int cza = cld(&E->cza), cza_layout = cld(&E->cza_layout);
-        const int ry_kind = cld(&E->ry_kind), ry_a = cld(&E->ry_a), ry_b = cld(&E->ry_b);
-        if constexpr (!BWD) {
-          if (perm_from >= 0) cx.perm(a, l, ph, perm_from, perm_to);
-          if (diag_layout >= 0)
-            cx.diagt(a, l, ph, diag_layout, cld(&E->czg_first), cld(&E->czg_count), cld(&E->pev_first), cld(&E->pev_count));
-          for (int i = 0; i < n_pha; ++i) cx.phasea(a, l, ph, cld(&A.phas[pha0 + i].regbit), cld(&A.phas[pha0 + i].pev));
-          if (cza >= 0) cx.cza(a, l, ph, cza, cza_layout);
-          if (ry_kind == 1) cx.ry(a, l, ph, ry_a, ry_b);
-          else if (ry_kind == 2) cx.ryg(a, l, ph, ry_a, ry_b);
-        } else {
-          const int n_func = cld(&E->func_count);
-          if (n_func > 0) cx.func(a, l, ph, n_func, cld(&E->func_first), cld(&E->func_full));
-          if (ry_kind == 1) cx.ry(a, l, ph, ry_a, ry_b);
-          else if (ry_kind == 2) cx.ryg(a, l, ph, ry_a, ry_b);
-          if (cza >= 0) cx.cza(a, l, ph, cza, cza_layout);
-          for (int i = 0; i < n_pha; ++i) cx.phasea(a, l, ph, cld(&A.phas[pha0 + i].regbit), cld(&A.phas[pha0 + i].pev));
-          if (diag_layout >= 0)
-            cx.diagt(a, l, ph, diag_layout, cld(&E->czg_first), cld(&E->czg_count), cld(&E->pev_first), cld(&E->pev_count));
-          if (perm_from >= 0) cx.perm(a, l, ph, perm_from, perm_to);
+        // a run of consecutive register epochs, one iteration each, with the
+        // sub-steps of an epoch in program order; every epoch has its PERM and
+        // applies its run group (mask 0: identity), so the loop body has one path
+        for (int ei = op.a; ei < op.a + op.b; ++ei) {
+          const EpochRec* E = A.epochs + ei;
+          const int perm_from = cld(&E->perm_from), perm_to = cld(&E->perm_to);
+          const int diag_layout = cld(&E->diag_layout);
+          const int n_pha = cld(&E->pha_count), pha0 = cld(&E->pha_first);
+          const int cza = cld(&E->cza), cza_layout = cld(&E->cza_layout);
+          const int ry_first = cld(&E->ry_a), ry_mask = cld(&E->ry_b);
+          if constexpr (!BWD) {
+            cx.perm(a, l, ph, perm_from, perm_to);
+            if (diag_layout >= 0)
+              cx.diagt(a, l, ph, diag_layout, cld(&E->czg_first), cld(&E->czg_count), cld(&E->pev_first),
+                       cld(&E->pev_count));
+            if (n_pha > 0) cx.phasea(a, l, ph, cld(&A.phas[pha0].regbit), cld(&A.phas[pha0].pev));
+            if (cza >= 0) cx.cza(a, l, ph, cza, cza_layout);
+            cx.ryg(a, l, ph, ry_first, ry_mask);
+          } else {
+            const int n_func = cld(&E->func_count);
+            if (n_func > 0) cx.func(a, l, ph, n_func, cld(&E->func_first), 0);
+            cx.ryg(a, l, ph, ry_first, ry_mask);
+            if (cza >= 0) cx.cza(a, l, ph, cza, cza_layout);
+            if (n_pha > 0) cx.phasea(a, l, ph, cld(&A.phas[pha0].regbit), cld(&A.phas[pha0].pev));
+            if (diag_layout >= 0)
+              cx.diagt(a, l, ph, diag_layout, cld(&E->czg_first), cld(&E->czg_count), cld(&E->pev_first),
+                       cld(&E->pev_count));
+            cx.perm(a, l, ph, perm_from, perm_to);
+          }
         }
         break;
       }
@@ -567,7 +579,8 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
 #pragma unroll
             for (int jj = 0; jj < NA; ++jj) {
               const uint32_t x = base | rb(jj);
-              const float p = fmaf(a[jj].x, a[jj].x, a[jj].y * a[jj].y);
+              // lanes beyond a small tile hold copies of in-tile elements
+              const float p = active ? fmaf(a[jj].x, a[jj].x, a[jj].y * a[jj].y) : 0.f;
 #pragma unroll
               for (int k = 0; k < 16; ++k)
                 if (k0 + k < A.K) v[k] += (__popc(x & cld(A.zmask + k0 + k)) & 1) ? -p : p;
@@ -614,7 +627,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
     // one partial sum per tile and functional: add the waves' sums
     if (n_slots > 0) {
       __syncthreads();
-      const float* part = reinterpret_cast<const float*>(lds + A.tile_elems);
+      const float* part = lds_part;
       for (int i = t; i < 3 * n_slots; i += NT) {
         float acc = 0.f;
 #pragma unroll

@@ -186,11 +186,11 @@ inline KArgs make_pass_args(const PlanCore& c, const PlanPtrs& d, const CoefPtrs
 
 inline unsigned pass_blocks(const PlanCore& c, int nb) { return (unsigned)((long long)nb << c.S.tiles_log2); }
 
-// LDS of a pass workgroup: the tile, then (backward) one partial sum per wave,
-// functional slot and Pauli.
+// Dynamic LDS of a pass workgroup (the tile itself is a static array of the
+// kernel): backward only, one partial sum per wave, functional slot and Pauli.
 inline size_t pass_shmem(const PlanCore& c, bool bwd) {
   const Schedule& S = c.S;
-  return (sizeof(float) * 2 << S.k) + (bwd ? sizeof(float) * 3 * S.max_slots * (S.NT / 64) : 0);
+  return bwd ? sizeof(float) * 3 * S.max_slots * (S.NT / 64) : 0;
 }
 
 inline CoefArgs make_coef_args(const PlanCore& c, const PlanPtrs& d, const float* theta, const float* x,

@@ -244,6 +244,7 @@ static void fuse_epochs(Schedule* Sp) {
   Schedule& S = *Sp;
   std::vector<Op> out;
   out.reserve(S.ops.size());
+  int cur_begin = 0;   // first op of the program being built (runs never cross programs)
   auto blank = []() {
     EpochRec e;
     std::memset(&e, 0, sizeof(e));
@@ -251,8 +252,15 @@ static void fuse_epochs(Schedule* Sp) {
     return e;
   };
   auto take_ry = [&](const Op& o, EpochRec* e) {
-    if (o.kind == OP_RY) { e->ry_kind = 1; e->ry_a = o.a; e->ry_b = o.b; }
-    else { e->ry_kind = 2; e->ry_a = o.b; e->ry_b = o.c; }
+    e->ry_kind = 2;
+    if (o.kind == OP_RY) {   // a single run becomes a group of one
+      e->ry_a = (int)S.rygs.size();
+      e->ry_b = 1 << o.a;
+      S.rygs.push_back({o.a, o.b});
+    } else {
+      e->ry_a = o.b;
+      e->ry_b = o.c;
+    }
   };
   auto take_phas = [&](int* j, int end, EpochRec* e) {
     e->pha_first = (int)S.phas.size();
@@ -265,12 +273,18 @@ static void fuse_epochs(Schedule* Sp) {
   auto take_diag = [&](const Op& o, EpochRec* e) {
     e->diag_layout = o.a; e->czg_first = o.b; e->czg_count = o.c; e->pev_first = o.d; e->pev_count = o.e;
   };
+  // consecutive epochs share one OP_EPOCH op (records are contiguous)
   auto emit = [&](const EpochRec& e) {
-    out.push_back({OP_EPOCH, (int)S.epochs.size(), 0, 0, 0, 0, 0, 0});
+    if (!out.empty() && out.back().kind == OP_EPOCH && out.back().a + out.back().b == (int)S.epochs.size() &&
+        (int)out.size() > cur_begin)
+      out.back().b++;
+    else
+      out.push_back({OP_EPOCH, (int)S.epochs.size(), 1, 0, 0, 0, 0, 0});
     S.epochs.push_back(e);
   };
   auto fwd = [&](int begin, int count, int* nb, int* nc) {
     *nb = (int)out.size();
+    cur_begin = *nb;
     const int end = begin + count;
     int i = begin;
     while (i < end) {
@@ -281,6 +295,12 @@ static void fuse_epochs(Schedule* Sp) {
       int j = i + 1;
       if (j < end && S.ops[j].kind == OP_DIAGT) take_diag(S.ops[j++], &e);
       take_phas(&j, end, &e);
+      if (e.pha_count > kEpochMaxPhaseA) {   // rare: leave this epoch's ops as they are
+        S.phas.resize(e.pha_first);
+        for (int q = i; q < j; ++q) out.push_back(S.ops[q]);
+        i = j;
+        continue;
+      }
       if (j < end && S.ops[j].kind == OP_CZA) { e.cza = S.ops[j].a; e.cza_layout = S.ops[j].b; ++j; }
       if (j < end && (S.ops[j].kind == OP_RY || S.ops[j].kind == OP_RYG)) take_ry(S.ops[j++], &e);
       emit(e);
@@ -290,6 +310,7 @@ static void fuse_epochs(Schedule* Sp) {
   };
   auto bwd = [&](int begin, int count, int* nb, int* nc) {
     *nb = (int)out.size();
+    cur_begin = *nb;
     const int end = begin + count;
     int i = begin;
     while (i < end) {
@@ -305,7 +326,17 @@ static void fuse_epochs(Schedule* Sp) {
       if (j < end && S.ops[j].kind == OP_CZA) { e.cza = S.ops[j].a; e.cza_layout = S.ops[j].b; ++j; }
       take_phas(&j, end, &e);
       if (j < end && S.ops[j].kind == OP_DIAGT) take_diag(S.ops[j++], &e);
-      if (j < end && S.ops[j].kind == OP_PERM) { e.perm_from = S.ops[j].a; e.perm_to = S.ops[j].b; ++j; }
+      if (!(j < end && S.ops[j].kind == OP_PERM) || e.pha_count > kEpochMaxPhaseA) {
+        // epochs are fused only with their PERM; otherwise the ops stay as they are
+        S.phas.resize(e.pha_first);
+        if (e.ry_kind == 2 && S.ops[i + (S.ops[i].kind == OP_FUNC ? 1 : 0)].kind == OP_RY) S.rygs.pop_back();
+        for (int q = i; q < j; ++q) out.push_back(S.ops[q]);
+        i = j;
+        continue;
+      }
+      e.perm_from = S.ops[j].a;
+      e.perm_to = S.ops[j].b;
+      ++j;
       emit(e);
       i = j;
     }

@@ -46,8 +46,9 @@ enum OpKind : int32_t {
                   // Im<lambda|P_q|psi> for P=X,Y,Z
   OP_RYG = 12,    // a=entries, b=first RygEntry, c=mask of their register bits: the RY of
                   // several runs on distinct register bits (they commute), bits ascending
-  OP_EPOCH = 13,  // a=EpochRec: one register epoch (PERM, DIAGT, PHASEA*, CZA, RY/RYG forward;
-                  // FUNC, RY/RYG, CZA, PHASEA*, DIAGT, PERM backward) in one loop iteration
+  OP_EPOCH = 13,  // a=first EpochRec, b=count: consecutive register epochs (PERM, DIAGT,
+                  // PHASEA*, CZA, RY group forward; FUNC, RY group, CZA, PHASEA*, DIAGT,
+                  // PERM backward), one loop iteration each
 };
 
 struct Op {
@@ -124,13 +125,15 @@ struct PhaEntry {
   int32_t regbit, pev;
 };
 
-// The sub-ops of one epoch; -1 / 0 fields mark sub-ops that are absent.
+// The sub-ops of one epoch; -1 / 0 fields mark sub-ops that are absent.  At
+// most kEpochMaxPhaseA PHASEA sub-ops (epochs with more stay unfused).
+constexpr int kEpochMaxPhaseA = 1;
 struct EpochRec {
   int32_t perm_from, perm_to;                          // PERM (from -1: none)
   int32_t diag_layout, czg_first, czg_count, pev_first, pev_count;   // DIAGT (layout -1: none)
   int32_t pha_first, pha_count;                        // PhaEntry range
   int32_t cza, cza_layout;                             // CZA (-1: none)
-  int32_t ry_kind, ry_a, ry_b;                         // 0 none; 1 RY(bit a, ref b); 2 RYG(first a, mask b)
+  int32_t ry_kind, ry_a, ry_b;                         // run group: first RygEntry a, bit mask b (0: none)
   int32_t func_count, func_first, func_full;           // FUNC (backward; func_full unused)
   int32_t pad;
 };

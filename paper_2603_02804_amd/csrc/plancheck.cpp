@@ -458,32 +458,34 @@ struct CpuExec {
     }
   }
 
-  // An epoch op as its sub-ops in execution order; any other op as itself.
+  // An epoch op as the sub-ops of its epochs in execution order; any other op
+  // as itself.
   std::vector<Op> expand_op(const Op& o, bool bwd) const {
     if (o.kind != OP_EPOCH) return {o};
     const Schedule& S = c.S;
-    if (o.a < 0 || o.a >= (int)S.epochs.size()) oob("epoch record");
-    const EpochRec& e = S.epochs[o.a];
-    std::vector<Op> perm, diag, pha, cza, ry, func;
-    if (e.perm_from >= 0) perm.push_back({OP_PERM, e.perm_from, e.perm_to, 0, 0, 0, 0, 0});
-    if (e.diag_layout >= 0)
-      diag.push_back({OP_DIAGT, e.diag_layout, e.czg_first, e.czg_count, e.pev_first, e.pev_count, 0, 0});
-    for (int i = 0; i < e.pha_count; ++i) {
-      if (e.pha_first + i >= (int)S.phas.size()) oob("epoch PHASEA entry");
-      pha.push_back({OP_PHASEA, S.phas[e.pha_first + i].regbit, S.phas[e.pha_first + i].pev, 0, 0, 0, 0, 0});
-    }
-    if (e.cza >= 0) cza.push_back({OP_CZA, e.cza, e.cza_layout, 0, 0, 0, 0, 0});
-    if (e.ry_kind == 1) ry.push_back({OP_RY, e.ry_a, e.ry_b, 0, 0, 0, 0, 0});
-    if (e.ry_kind == 2) {
-      int cnt = 0;
-      for (int j = 0; j < 32; ++j) cnt += (e.ry_b >> j) & 1;
-      ry.push_back({OP_RYG, cnt, e.ry_a, e.ry_b, 0, 0, 0, 0});
-    }
-    if (e.func_count > 0) func.push_back({OP_FUNC, e.func_count, e.func_first, e.func_full, 0, 0, 0, 0});
     std::vector<Op> out;
-    auto add = [&](const std::vector<Op>& v) { out.insert(out.end(), v.begin(), v.end()); };
-    if (!bwd) { add(perm); add(diag); add(pha); add(cza); add(ry); }
-    else { add(func); add(ry); add(cza); add(pha); add(diag); add(perm); }
+    if (o.b < 1 || o.a < 0 || o.a + o.b > (int)S.epochs.size()) oob("epoch records");
+    for (int ei = o.a; ei < o.a + o.b; ++ei) {
+      const EpochRec& e = S.epochs[ei];
+      std::vector<Op> perm, diag, pha, cza, ry, func;
+      if (e.perm_from >= 0) perm.push_back({OP_PERM, e.perm_from, e.perm_to, 0, 0, 0, 0, 0});
+      if (e.diag_layout >= 0)
+        diag.push_back({OP_DIAGT, e.diag_layout, e.czg_first, e.czg_count, e.pev_first, e.pev_count, 0, 0});
+      for (int i = 0; i < e.pha_count; ++i) {
+        if (e.pha_first + i >= (int)S.phas.size()) oob("epoch PHASEA entry");
+        pha.push_back({OP_PHASEA, S.phas[e.pha_first + i].regbit, S.phas[e.pha_first + i].pev, 0, 0, 0, 0, 0});
+      }
+      if (e.cza >= 0) cza.push_back({OP_CZA, e.cza, e.cza_layout, 0, 0, 0, 0, 0});
+      if (e.ry_b != 0) {
+        int cnt = 0;
+        for (int j = 0; j < 32; ++j) cnt += (e.ry_b >> j) & 1;
+        ry.push_back({OP_RYG, cnt, e.ry_a, e.ry_b, 0, 0, 0, 0});
+      }
+      if (e.func_count > 0) func.push_back({OP_FUNC, e.func_count, e.func_first, 0, 0, 0, 0, 0});
+      auto add = [&](const std::vector<Op>& v) { out.insert(out.end(), v.begin(), v.end()); };
+      if (!bwd) { add(perm); add(diag); add(pha); add(cza); add(ry); }
+      else { add(func); add(ry); add(cza); add(pha); add(diag); add(perm); }
+    }
     return out;
   }
 

@@ -38,7 +38,7 @@
 namespace qf {
 
 template <int R, int NT, bool BWD>
-__global__ __launch_bounds__(NT, pass_min_waves<R>()) void k_pass(const KArgs A) {
+__global__ __launch_bounds__(NT, (pass_min_waves<R, BWD>())) void k_pass(const KArgs A) {
   pass_body<R, NT, BWD>(A, blockIdx.x);
 }
 
