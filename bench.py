@@ -112,8 +112,7 @@ def main() -> int:
                                  args.reg_qubits)) else "default"
     if tuning_src == "default" and not args.no_autotune:
         from paper_2603_02804_amd import autotune
-        cached = autotune.cached_tuning(w.n_qubits, w.gates, w.n_obs, B,
-                                        torch.cuda.get_device_name(dev).replace(" ", "_"))
+        cached = autotune.cached_tuning(w.n_qubits, w.gates, w.n_obs, B, autotune.device_key(dev))
         if cached:
             tun = autotune.tuning_from(cached)
             tuning_src = "autotuned (paper_2603_02804_amd/tuned_configs.json)"

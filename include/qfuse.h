@@ -80,9 +80,19 @@ typedef struct {
   int32_t n_obs;
 } qf_circuit_desc;
 
+/* Execution modes (qf_tuning.mode). */
+typedef enum {
+  QF_MODE_FUSED = 0,     /* fused forward and adjoint passes, complex64 (the method)      */
+  QF_MODE_PER_GATE = 1,  /* one kernel per gate, complex64: the unfused baseline          */
+  QF_MODE_C128 = 2       /* one kernel per gate, complex128, double inputs and outputs:
+                            validation only, called through qf_forward_c128 /
+                            qf_backward_c128; the other tuning fields except micro_batch
+                            are ignored                                                   */
+} qf_mode;
+
 /* Execution choices.  0 (or -1 for store_ckpt) selects the built-in default. */
 typedef struct {
-  int32_t mode;             /* 0 = fused passes, 1 = one kernel per gate (baseline)   */
+  int32_t mode;             /* qf_mode: 0 fused, 1 per-gate baseline, 2 complex128     */
   int32_t tile_qubits;      /* k: amplitudes per workgroup tile = 2^k, k <= 13         */
   int32_t reg_qubits;       /* r: register-resident qubits per lane (1..5)             */
   int32_t fusion_depth;     /* max rotation runs applied to one qubit in one pass      */
@@ -149,6 +159,25 @@ qf_status qf_forward(qf_plan* plan, const float* theta, const float* x, float* E
  */
 qf_status qf_backward(qf_plan* plan, const float* theta, const float* x, const float* dE,
                       float* dtheta, float* dx, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Complex128 validation path (plans created with mode QF_MODE_C128).  The same
+ * quantities as qf_forward / qf_backward (Sec. 2.1 expectations; Sec. 2.2
+ * adjoint gradients, eq. grad_theta and eq. update_adjoint_state) computed in
+ * double precision throughout, one kernel per gate: the state is complex128 and
+ * theta, x, E, dE, dtheta and dx are device double arrays with the layouts of
+ * the float calls.  Each gate's gradient is taken at the cut after the gate
+ * (dL/dtheta = 1/2 Im<lambda|P|psi>) before the gate is un-applied from psi and
+ * lambda.  Meant for checking the float paths and for finite-difference
+ * gradient checks, not for speed.  The float calls reject such a plan with
+ * QF_ERR_INVALID_ARG, and these calls reject any other plan the same way.
+ * Workspace: qf_workspace_size of the plan (final states of the batch, two
+ * working states per micro-batch sample, partial sums, coefficient tables).
+ */
+qf_status qf_forward_c128(qf_plan* plan, const double* theta, const double* x, double* E,
+                          void* ws, size_t ws_bytes, void* stream);
+qf_status qf_backward_c128(qf_plan* plan, const double* theta, const double* x, const double* dE,
+                           double* dtheta, double* dx, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Kernel timing for accounting.  While enabled, every launch the plan makes is

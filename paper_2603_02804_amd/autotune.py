@@ -64,6 +64,16 @@ def circuit_key(n_qubits: int, gates: np.ndarray, n_obs: int, batch: int, device
     return f"n{n_qubits}-g{len(gates)}-{h}-k{n_obs}-b{batch}-{device}"
 
 
+def device_key(dev=None) -> str:
+    """Cache key of a GPU: its ISA name and compute-unit count (the marketing name
+    that the runtime reports depends on the host's device-id tables)."""
+    import torch
+
+    p = torch.cuda.get_device_properties(dev if dev is not None else torch.device("cuda"))
+    arch = getattr(p, "gcnArchName", "") or p.name.replace(" ", "_")
+    return f"{arch.split(':')[0]}-cu{p.multi_processor_count}"
+
+
 def _load_cache(path: str) -> dict:
     if os.path.exists(path):
         with open(path) as f:
@@ -93,7 +103,7 @@ def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequen
 
     gates = np.ascontiguousarray(gates, dtype=np.int32).reshape(-1, 5)
     dev = torch.device("cuda")
-    name = torch.cuda.get_device_name(dev).replace(" ", "_") or "gpu"
+    name = device_key(dev)
     G = len(gates)
     pre = gates[: min(G, prefix_gates)]
     P_used = int(pre[:, 3].max()) + 1 if (pre[:, 3] >= 0).any() else 0

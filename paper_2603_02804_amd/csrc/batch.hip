@@ -20,6 +20,7 @@
 
 #include "batch.hpp"
 #include "device.hpp"
+#include "small_kernels.hpp"
 #include "gpu_plan.hpp"
 
 namespace qf {

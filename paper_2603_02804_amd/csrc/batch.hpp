@@ -19,7 +19,7 @@
 #include <string>
 #include <vector>
 
-#include "kargs.hpp"
+#include "small_args.hpp"
 
 namespace qf {
 
@@ -102,7 +102,7 @@ struct RecordExec {
   }
   void reduce_E(int nb, int sample0, const float* partE, float*) {
     SmallJob j = job(SJ_REDUCE_E, circ);
-    j.u.re = make_reduce_E_args(c, nb, sample0, c.tiles * c.waves, partE, nullptr);
+    j.u.re = make_reduce_E_args<float>(c, nb, sample0, c.tiles * c.waves, partE, nullptr);
     small(j, blocks_for((long long)nb * c.C.K), 0);
   }
   void assemble(int seg, int nb, int sample0, const float*, const float*, const float* partF, float* Gr) {
@@ -113,7 +113,7 @@ struct RecordExec {
   }
   void reduce_grads(int nb, int sample0, const float* Gr, float*, float*, bool accumulate) {
     SmallJob j = job(SJ_REDUCE_G, circ);
-    j.u.rg = make_reduce_grads_args(c, d, nb, sample0, Gr, nullptr, nullptr, accumulate);
+    j.u.rg = make_reduce_grads_args<float>(c, d, nb, sample0, Gr, nullptr, nullptr, accumulate);
     const long long n = reduce_grads_items(j.u.rg);
     if (n > 0) small(j, blocks_for(n), 0);
   }

@@ -41,7 +41,8 @@ struct PlanCore {
   Tuning T;
   Schedule S;
   int B = 0;
-  bool per_gate = false;
+  bool per_gate = false;              // one kernel per gate (float baseline or complex128)
+  bool c128 = false;                  // complex128 validation path (double throughout)
   int P = 0, ckpt = 1, n_seg = 1, mb = 1, store = 1;
   int waves = 1, tiles = 1;
   int64_t amps = 1;                   // 2^n
@@ -83,9 +84,11 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
   c.C = C;
   c.T = T;
   c.B = B;
-  c.per_gate = (T.mode == 1);
+  c.per_gate = (T.mode == 1 || T.mode == 2);
+  c.c128 = (T.mode == 2);
+  const size_t real_bytes = c.c128 ? sizeof(double) : sizeof(float);
   c.amps = int64_t(1) << C.n;
-  c.state_bytes = size_t(8) << C.n;
+  c.state_bytes = (2 * real_bytes) << C.n;
   if (c.per_gate) {
     build_gate_runs(C, &c.S);
     c.S.n = C.n;
@@ -114,16 +117,17 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
     const int64_t per_block = int64_t(kPgThreads) * kPgPairsPerThread;
     c.pg_blocks = (int)((pairs + per_block - 1) / per_block);
     c.pg_chunk = std::max(1, std::min(c.n_angle, 4096));
+    const size_t rb = real_bytes;
     size_t off = 0;
-    c.off_coef_sh = off; off = align_up(off + sizeof(float) * 8 * std::max(1, S.n_coef_shared));
-    c.off_coef_ps = off; off = align_up(off + sizeof(float) * 8 * std::max<int64_t>(1, int64_t(B) * S.n_coef_ps));
-    c.off_ev_sh = off;   off = align_up(off + sizeof(float) * 2);
-    c.off_ev_ps = off;   off = align_up(off + sizeof(float) * 2);
+    c.off_coef_sh = off; off = align_up(off + rb * 8 * std::max(1, S.n_coef_shared));
+    c.off_coef_ps = off; off = align_up(off + rb * 8 * std::max<int64_t>(1, int64_t(B) * S.n_coef_ps));
+    c.off_ev_sh = off;   off = align_up(off + rb * 2);
+    c.off_ev_ps = off;   off = align_up(off + rb * 2);
     c.off_ckpt = off;    off = align_up(off + SB * B);            // final states of the batch
     c.off_lam = off;     off = align_up(off + SB * 2 * c.mb);     // psi copy + lambda
-    c.off_partE = off;   off = align_up(off + sizeof(float) * std::max<int64_t>(1, int64_t(c.mb) * c.pg_blocks * C.K));
-    c.off_partF = off;   off = align_up(off + sizeof(float) * int64_t(c.mb) * c.pg_chunk * c.pg_blocks * 3);
-    c.off_Gr = off;      off = align_up(off + sizeof(float) * std::max<int64_t>(1, int64_t(c.mb) * c.n_angle));
+    c.off_partE = off;   off = align_up(off + rb * std::max<int64_t>(1, int64_t(c.mb) * c.pg_blocks * C.K));
+    c.off_partF = off;   off = align_up(off + rb * int64_t(c.mb) * c.pg_chunk * c.pg_blocks * 3);
+    c.off_Gr = off;      off = align_up(off + rb * std::max<int64_t>(1, int64_t(c.mb) * c.n_angle));
     c.ws_bytes = off;
     return QF_OK;
   }
@@ -199,43 +203,44 @@ inline T* at(char* ws, size_t off) {
 // gate (un-applying it), plus the gate's functional partial sums.  This is the
 // unfused reference point for the fused passes (Sec. 3.1: every gate touches
 // O(2^n) amplitudes).
-template <class Exec>
-qf_status run_forward_pg(const PlanCore& c, Exec& ex, const float* theta, const float* x, float* E, char* ws) {
+// Real is float on the baseline and double on the complex128 validation path.
+template <class Real, class Exec>
+qf_status run_forward_pg(const PlanCore& c, Exec& ex, const Real* theta, const Real* x, Real* E, char* ws) {
   const int64_t SA = 2 * c.amps;
-  const float* csh = at<float>(ws, c.off_coef_sh);
-  const float* cps = at<float>(ws, c.off_coef_ps);
-  ex.coef(theta, x, ws);
+  const Real* csh = at<Real>(ws, c.off_coef_sh);
+  const Real* cps = at<Real>(ws, c.off_coef_ps);
+  ex.pg_coef(theta, x, ws);
   for (int mb0 = 0; mb0 < c.B; mb0 += c.mb) {
     const int nb = std::min(c.mb, c.B - mb0);
-    float* psi = at<float>(ws, c.off_ckpt) + int64_t(mb0) * SA;
+    Real* psi = at<Real>(ws, c.off_ckpt) + int64_t(mb0) * SA;
     ex.pg_init(psi, nb);
     int r = 0;
     for (const qf_gate& g : c.C.gates) {
-      if (g.kind == QF_CZ) ex.pg_cz(psi, nullptr, nb, g.q0, g.q1);
+      if (g.kind == QF_CZ) ex.pg_cz(psi, (Real*)nullptr, nb, g.q0, g.q1);
       else ex.pg_rot(psi, nb, mb0, r++, csh, cps);
     }
-    ex.pg_expect(psi, nb, at<float>(ws, c.off_partE));
-    ex.pg_reduce_E(nb, mb0, at<float>(ws, c.off_partE), E);
+    ex.pg_expect((const Real*)psi, nb, at<Real>(ws, c.off_partE));
+    ex.pg_reduce_E(nb, mb0, (const Real*)at<Real>(ws, c.off_partE), E);
   }
   return ex.status();
 }
 
-template <class Exec>
-qf_status run_backward_pg(const PlanCore& c, Exec& ex, const float* /*theta*/, const float* /*x*/, const float* dE,
-                          float* dtheta, float* dx, char* ws) {
+template <class Real, class Exec>
+qf_status run_backward_pg(const PlanCore& c, Exec& ex, const Real* theta, const Real* x, const Real* dE,
+                          Real* dtheta, Real* dx, char* ws) {
   const int64_t SA = 2 * c.amps;
-  const float* csh = at<float>(ws, c.off_coef_sh);
-  const float* cps = at<float>(ws, c.off_coef_ps);
-  float* partF = at<float>(ws, c.off_partF);
-  float* Gr = at<float>(ws, c.off_Gr);
+  const Real* csh = at<Real>(ws, c.off_coef_sh);
+  const Real* cps = at<Real>(ws, c.off_coef_ps);
+  Real* partF = at<Real>(ws, c.off_partF);
+  Real* Gr = at<Real>(ws, c.off_Gr);
   const int nrot = c.n_angle;
   for (int mb0 = 0; mb0 < c.B; mb0 += c.mb) {
     const int nb = std::min(c.mb, c.B - mb0);
-    const float* fin = at<float>(ws, c.off_ckpt) + int64_t(mb0) * SA;
-    float* psi = at<float>(ws, c.off_lam);
-    float* lam = psi + SA * nb;
+    const Real* fin = at<Real>(ws, c.off_ckpt) + int64_t(mb0) * SA;
+    Real* psi = at<Real>(ws, c.off_lam);
+    Real* lam = psi + SA * nb;
     ex.pg_copy(psi, fin, nb);
-    ex.pg_seed(psi, lam, nb, mb0, dE);
+    ex.pg_seed((const Real*)psi, lam, nb, mb0, dE);
     int r = nrot;
     for (int64_t j = (int64_t)c.C.gates.size() - 1; j >= 0; --j) {
       const qf_gate& g = c.C.gates[j];
@@ -247,10 +252,10 @@ qf_status run_backward_pg(const PlanCore& c, Exec& ex, const float* /*theta*/, c
       ex.pg_rot_bwd(psi, lam, nb, mb0, r, r % c.pg_chunk, csh, cps, partF);
       if (r % c.pg_chunk == 0) {
         const int cnt = std::min(c.pg_chunk, nrot - r);
-        ex.pg_assemble(r, cnt, nb, mb0, partF, Gr);
+        ex.pg_assemble(r, cnt, nb, mb0, theta, x, (const Real*)partF, Gr);
       }
     }
-    ex.reduce_grads(nb, mb0, Gr, dtheta, dx, mb0 > 0);
+    ex.pg_reduce_grads(nb, mb0, (const Real*)Gr, dtheta, dx, mb0 > 0);
   }
   return ex.status();
 }

@@ -1,5 +1,5 @@
-// kargs.hpp -- argument records of the device kernels and the host code that
-// fills them from a plan.  Plain structs of pointers and integers, shared by the
+// kargs.hpp -- argument record of the fused pass kernels and the host code that
+// fills it from a plan.  Plain structs of pointers and integers, shared by the
 // single-plan launch backend, the merged mixed-batch programs and the CPU checker.
 #pragma once
 #include <stdint.h>
@@ -80,53 +80,6 @@ struct KArgs {
   int tile_elems;             // 2^k: LDS elements of the tile; wave partial sums follow
 };
 
-struct CoefArgs {
-  Tabs T;
-  const float* theta;
-  const float* x;
-  float* csh;
-  float* cps;
-  int F, n_sh, n_ps, B, zyz;
-};
-
-struct EventArgs {
-  Tabs T;
-  const float* csh;
-  const float* cps;
-  float* esh;
-  float* eps;
-  int n_ev_sh, n_ev_ps, B, n_ps;
-};
-
-struct ReduceEArgs {
-  const float* partE;
-  float* E;
-  int nb, sample0, parts, K;
-};
-
-struct AssembleArgs {
-  Tabs T;
-  const float* theta;
-  const float* x;
-  const float* partF;
-  float* Gr;
-  int p0, np, nb, sample0, tiles, n_angle, F;
-};
-
-struct ReduceGArgs {
-  Tabs T;
-  const float* Gr;
-  float* dtheta;
-  float* dx;
-  int nb, sample0, n_angle, P, F, accumulate;
-};
-
-constexpr int kSmallThreads = 256;
-
-inline unsigned blocks_for(long long n, int t = kSmallThreads) {
-  return (unsigned)std::max<long long>(1, (n + t - 1) / t);
-}
-
 // Workspace addresses of the coefficient tables of one call.
 struct CoefPtrs {
   const float* csh = nullptr;
@@ -192,125 +145,5 @@ inline size_t pass_shmem(const PlanCore& c, bool bwd) {
   const Schedule& S = c.S;
   return bwd ? sizeof(float) * 3 * S.max_slots * (S.NT / 64) : 0;
 }
-
-inline CoefArgs make_coef_args(const PlanCore& c, const PlanPtrs& d, const float* theta, const float* x,
-                               const CoefPtrs& cp) {
-  CoefArgs a;
-  a.T = d.tabs;
-  a.theta = theta;
-  a.x = x;
-  a.csh = const_cast<float*>(cp.csh);
-  a.cps = const_cast<float*>(cp.cps);
-  a.F = c.C.F;
-  a.n_sh = c.S.n_coef_shared;
-  a.n_ps = c.S.n_coef_ps;
-  a.B = c.B;
-  a.zyz = c.per_gate ? 0 : 1;
-  return a;
-}
-
-inline long long coef_items(const CoefArgs& a) { return a.n_sh + (long long)a.n_ps * a.B; }
-
-inline EventArgs make_event_args(const PlanCore& c, const PlanPtrs& d, const CoefPtrs& cp) {
-  EventArgs a;
-  a.T = d.tabs;
-  a.csh = cp.csh;
-  a.cps = cp.cps;
-  a.esh = const_cast<float*>(cp.esh);
-  a.eps = const_cast<float*>(cp.eps);
-  a.n_ev_sh = c.S.n_ev_shared;
-  a.n_ev_ps = c.S.n_ev_ps;
-  a.B = c.B;
-  a.n_ps = c.S.n_coef_ps;
-  return a;
-}
-
-inline long long event_items(const EventArgs& a) { return a.n_ev_sh + (long long)a.n_ev_ps * a.B; }
-
-inline ReduceEArgs make_reduce_E_args(const PlanCore& c, int nb, int sample0, int parts, const float* partE,
-                                      float* E) {
-  ReduceEArgs a;
-  a.partE = partE;
-  a.E = E;
-  a.nb = nb;
-  a.sample0 = sample0;
-  a.parts = parts;
-  a.K = c.C.K;
-  return a;
-}
-
-inline AssembleArgs make_assemble_args(const PlanCore& c, const PlanPtrs& d, int seg, int nb, int sample0,
-                                       const float* theta, const float* x, const float* partF, float* Gr) {
-  AssembleArgs a;
-  a.T = d.tabs;
-  a.theta = theta;
-  a.x = x;
-  a.partF = partF;
-  a.Gr = Gr;
-  a.p0 = c.seg_begin[seg];
-  a.np = c.seg_begin[seg + 1] - a.p0;
-  a.nb = nb;
-  a.sample0 = sample0;
-  a.tiles = c.tiles;
-  a.n_angle = c.n_angle;
-  a.F = c.C.F;
-  return a;
-}
-
-inline size_t assemble_shmem(const PlanCore& c) { return sizeof(double) * 3 * std::max(1, c.S.max_slots); }
-
-inline ReduceGArgs make_reduce_grads_args(const PlanCore& c, const PlanPtrs& d, int nb, int sample0,
-                                          const float* Gr, float* dtheta, float* dx, bool accumulate) {
-  ReduceGArgs a;
-  a.T = d.tabs;
-  a.Gr = Gr;
-  a.dtheta = dtheta;
-  a.dx = dx;
-  a.nb = nb;
-  a.sample0 = sample0;
-  a.n_angle = c.n_angle;
-  a.P = c.C.P;
-  a.F = c.C.F;
-  a.accumulate = accumulate ? 1 : 0;
-  return a;
-}
-
-inline long long reduce_grads_items(const ReduceGArgs& a) { return a.P + (long long)a.nb * a.F; }
-
-// ---------------------------------------------------------------- mixed batches
-// Caller buffers of one circuit of a mixed batch, refreshed on every call.
-struct CircPtrs {
-  const float* theta;
-  const float* x;
-  float* E;
-  const float* dE;
-  float* dtheta;
-  float* dx;
-};
-
-// A pass launch of one circuit inside a merged launch.  Workspace addresses are
-// stored as offsets from the batch workspace base (never 0: the first bytes of
-// the workspace are reserved), null stays null; dE comes from CircPtrs.
-struct PassJob {
-  KArgs A;
-  int32_t circ;
-  int32_t pass;       // pass index in the circuit's plan (host checks only)
-};
-
-enum SmallKind : int32_t { SJ_COEF = 0, SJ_EVENT = 1, SJ_REDUCE_E = 2, SJ_ASSEMBLE = 3, SJ_REDUCE_G = 4 };
-
-// A small-kernel launch of one circuit inside a merged launch: same address
-// convention; theta, x, E, dtheta and dx come from CircPtrs.
-struct SmallJob {
-  int32_t kind;
-  int32_t circ;
-  union {
-    CoefArgs coef;
-    EventArgs ev;
-    ReduceEArgs re;
-    AssembleArgs as;
-    ReduceGArgs rg;
-  } u;
-};
 
 }  // namespace qf

@@ -547,6 +547,10 @@ struct CpuExec {
   }
 
   // ---------------------------------------------------------------- per-gate baseline
+  void pg_coef(const float* th, const float* xx, char* ws) { coef(th, xx, ws); }
+  void pg_reduce_grads(int nb, int sample0, const float* Gr, float* dtheta, float* dx, bool accumulate) {
+    reduce_grads(nb, sample0, Gr, dtheta, dx, accumulate);
+  }
   void pg_init(float* psi, int nb) {
     for (int s = 0; s < nb; ++s) {
       std::memset(psi + s * 2 * c.amps, 0, sizeof(float) * 2 * c.amps);
@@ -638,7 +642,7 @@ struct CpuExec {
       apply1(Lm, q, ud);
     }
   }
-  void pg_assemble(int r0, int cnt, int nb, int sample0, const float* partF, float* Gr) {
+  void pg_assemble(int r0, int cnt, int nb, int sample0, const float*, const float*, const float* partF, float* Gr) {
     for (int s = 0; s < nb; ++s)
       for (int i = 0; i < cnt; ++i) {
         const int r = r0 + i, slot = r % c.pg_chunk;
@@ -676,6 +680,7 @@ int qfc_run(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tuning,
       T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
       T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt;
     }
+    if (T.mode == 2) { g_err = "the checker runs float plans only"; return QF_ERR_UNSUPPORTED; }
     PlanCore pc;
     st = build_plan_core(C, batch, T, &pc, &msg);
     if (st != QF_OK) { g_err = msg; return st; }

@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "device.hpp"
+#include "small_kernels.hpp"
 #include "gpu_plan.hpp"
 
 namespace qf {
@@ -42,7 +43,8 @@ __global__ __launch_bounds__(NT, (pass_min_waves<R, BWD>())) void k_pass(const K
   pass_body<R, NT, BWD>(A, blockIdx.x);
 }
 
-__global__ __launch_bounds__(kSmallThreads) void k_coef(const CoefArgs a) {
+template <class Real>
+__global__ __launch_bounds__(kSmallThreads) void k_coef(const CoefArgsT<Real> a) {
   coef_body(a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
@@ -55,47 +57,86 @@ __global__ __launch_bounds__(kSmallThreads) void k_assemble(const AssembleArgs a
   assemble_body(a, blockIdx.x, fsum);
 }
 
-__global__ __launch_bounds__(kSmallThreads) void k_reduce_grads(const ReduceGArgs a) {
+template <class Real>
+__global__ __launch_bounds__(kSmallThreads) void k_reduce_grads(const ReduceGArgsT<Real> a) {
   reduce_grads_body(a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-__global__ __launch_bounds__(kSmallThreads) void k_reduce_E(const ReduceEArgs a) {
+template <class Real>
+__global__ __launch_bounds__(kSmallThreads) void k_reduce_E(const ReduceEArgsT<Real> a) {
   reduce_E_body(a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
-// per-gate baseline kernels
+// per-gate kernels: the unfused baseline (float) and the complex128
+// validation path (double) share them
 // ---------------------------------------------------------------------------
+template <class Real> struct Cplx;
+template <> struct Cplx<float> {
+  using T = float2;
+  static __device__ __forceinline__ T make(float a, float b) { return make_float2(a, b); }
+};
+template <> struct Cplx<double> {
+  using T = double2;
+  static __device__ __forceinline__ T make(double a, double b) { return make_double2(a, b); }
+};
+
 __device__ __forceinline__ long long pair_lo(long long p, int q) {
   return ((p >> q) << (q + 1)) | (p & ((1ll << q) - 1));
 }
 
-__global__ void k_pg_init(float2* psi, long long amps, int nb) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= amps * nb) return;
-  psi[i] = make_float2((i % amps) == 0 ? 1.f : 0.f, 0.f);
+// (x0, x1) <- M (x0, x1) for a 2x2 complex M given row-major as 8 reals
+template <class Real, class V>
+__device__ __forceinline__ void mat2_apply(const Real (&m)[8], V& x0, V& x1) {
+  const V y0 = Cplx<Real>::make(m[0] * x0.x - m[1] * x0.y + m[2] * x1.x - m[3] * x1.y,
+                                m[0] * x0.y + m[1] * x0.x + m[2] * x1.y + m[3] * x1.x);
+  const V y1 = Cplx<Real>::make(m[4] * x0.x - m[5] * x0.y + m[6] * x1.x - m[7] * x1.y,
+                                m[4] * x0.y + m[5] * x0.x + m[6] * x1.y + m[7] * x1.x);
+  x0 = y0;
+  x1 = y1;
 }
 
-__global__ __launch_bounds__(kPgThreads) void k_pg_rot(float2* psi, long long amps, int q, int ref, int sample0,
-                                                       const float* csh, const float* cps, int n_ps, int blocks) {
+template <class Real>
+__device__ __forceinline__ const Real* pg_coef_row(const Real* csh, const Real* cps, int ref, int sample, int n_ps) {
+  return ref >= 0 ? csh + 8 * (long long)ref : cps + 8 * ((long long)sample * n_ps + (-1 - ref));
+}
+
+template <class Real>
+__global__ void k_pg_init(typename Cplx<Real>::T* psi, long long amps, int nb) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= amps * nb) return;
+  psi[i] = Cplx<Real>::make((i % amps) == 0 ? 1 : 0, 0);
+}
+
+template <class Real>
+__global__ __launch_bounds__(kPgThreads) void k_pg_rot(typename Cplx<Real>::T* psi, long long amps, int q, int ref,
+                                                       int sample0, const Real* csh, const Real* cps, int n_ps,
+                                                       int blocks) {
+  using V = typename Cplx<Real>::T;
   const int s = blockIdx.x / blocks, blk = blockIdx.x - s * blocks;
-  float2* v = psi + (long long)s * amps;
-  const float* c = ref >= 0 ? csh + 8 * (long long)ref : cps + 8 * ((long long)(sample0 + s) * n_ps + (-1 - ref));
-  const float r00 = c[0], i00 = c[1], r01 = c[2], i01 = c[3], r10 = c[4], i10 = c[5], r11 = c[6], i11 = c[7];
+  V* v = psi + (long long)s * amps;
+  const Real* c = pg_coef_row(csh, cps, ref, sample0 + s, n_ps);
+  Real m[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) m[i] = c[i];
   const long long pairs = amps >> 1;
 #pragma unroll
   for (int k = 0; k < kPgPairsPerThread; ++k) {
     const long long p = ((long long)blk * kPgPairsPerThread + k) * kPgThreads + threadIdx.x;
     if (p >= pairs) break;
     const long long i0 = pair_lo(p, q), i1 = i0 | (1ll << q);
-    const float2 x0 = v[i0], x1 = v[i1];
-    v[i0] = make_float2(r00 * x0.x - i00 * x0.y + r01 * x1.x - i01 * x1.y, r00 * x0.y + i00 * x0.x + r01 * x1.y + i01 * x1.x);
-    v[i1] = make_float2(r10 * x0.x - i10 * x0.y + r11 * x1.x - i11 * x1.y, r10 * x0.y + i10 * x0.x + r11 * x1.y + i11 * x1.x);
+    V x0 = v[i0], x1 = v[i1];
+    mat2_apply(m, x0, x1);
+    v[i0] = x0;
+    v[i1] = x1;
   }
 }
 
 // CZ touches only the quarter of the amplitudes with both bits set.
-__global__ void k_pg_cz(float2* psi, float2* lam, long long amps, int qa, int qb, int nb) {
+template <class Real>
+__global__ void k_pg_cz(typename Cplx<Real>::T* psi, typename Cplx<Real>::T* lam, long long amps, int qa, int qb,
+                        int nb) {
+  using V = typename Cplx<Real>::T;
   const long long quarter = amps >> 2;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= quarter * nb) return;
@@ -104,43 +145,45 @@ __global__ void k_pg_cz(float2* psi, float2* lam, long long amps, int qa, int qb
   long long i = pair_lo(j, lo);
   i = pair_lo(i, hi);
   i |= (1ll << lo) | (1ll << hi);
-  float2* v = psi + s * amps + i;
-  *v = make_float2(-v->x, -v->y);
+  V* v = psi + s * amps + i;
+  *v = Cplx<Real>::make(-v->x, -v->y);
   if (lam) {
-    float2* w = lam + s * amps + i;
-    *w = make_float2(-w->x, -w->y);
+    V* w = lam + s * amps + i;
+    *w = Cplx<Real>::make(-w->x, -w->y);
   }
 }
 
 // Block sum of NV per-thread values; writes the first `count` sums to out[0..count).
-template <int NV>
-__device__ inline void block_reduce(float (&v)[NV], float* out, int count) {
-  __shared__ float sm[NV][kPgThreads / 64];
+template <int NV, class Real>
+__device__ inline void block_reduce(Real (&v)[NV], Real* out, int count) {
+  __shared__ Real sm[NV][kPgThreads / 64];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    float x = v[k];
+    Real x = v[k];
     for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m);
     if ((threadIdx.x & 63) == 0) sm[k][threadIdx.x >> 6] = x;
   }
   __syncthreads();
   if ((int)threadIdx.x < NV && (int)threadIdx.x < count) {
-    float acc = 0;
+    Real acc = 0;
     for (int w = 0; w < kPgThreads / 64; ++w) acc += sm[threadIdx.x][w];
     out[threadIdx.x] = acc;
   }
 }
 
-__global__ __launch_bounds__(kPgThreads) void k_pg_expect(const float2* psi, long long amps, int K,
-                                                          const uint32_t* zmask, float* partE, int blocks) {
+template <class Real>
+__global__ __launch_bounds__(kPgThreads) void k_pg_expect(const typename Cplx<Real>::T* psi, long long amps, int K,
+                                                          const uint32_t* zmask, Real* partE, int blocks) {
+  using V = typename Cplx<Real>::T;
   const int s = blockIdx.x / blocks, blk = blockIdx.x - s * blocks;
-  const float2* v = psi + (long long)s * amps;
+  const V* v = psi + (long long)s * amps;
   for (int k0 = 0; k0 < K; k0 += 8) {
-    float acc[8];
+    Real acc[8];
     for (int k = 0; k < 8; ++k) acc[k] = 0;
     for (int k2 = 0; k2 < 2 * kPgPairsPerThread; ++k2) {
       const long long i = ((long long)blk * 2 * kPgPairsPerThread + k2) * kPgThreads + threadIdx.x;
       if (i >= amps) break;
-      const float p = v[i].x * v[i].x + v[i].y * v[i].y;
+      const Real p = v[i].x * v[i].x + v[i].y * v[i].y;
       for (int k = 0; k < 8; ++k)
         if (k0 + k < K) acc[k] += (__popcll((unsigned long long)i & zmask[k0 + k]) & 1) ? -p : p;
     }
@@ -149,49 +192,58 @@ __global__ __launch_bounds__(kPgThreads) void k_pg_expect(const float2* psi, lon
   }
 }
 
-__global__ void k_pg_seed(const float2* psi, float2* lam, long long amps, int nb, int sample0, int K,
-                          const uint32_t* zmask, const float* dE) {
+template <class Real>
+__global__ void k_pg_seed(const typename Cplx<Real>::T* psi, typename Cplx<Real>::T* lam, long long amps, int nb,
+                          int sample0, int K, const uint32_t* zmask, const Real* dE) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= amps * nb) return;
   const long long s = idx / amps, i = idx - s * amps;
-  float c = 0;
+  Real c = 0;
   for (int k = 0; k < K; ++k) {
-    const float g = dE[(sample0 + s) * K + k];
+    const Real g = dE[(sample0 + s) * K + k];
     c += (__popcll((unsigned long long)i & zmask[k]) & 1) ? -g : g;
   }
-  lam[idx] = make_float2(2.f * c * psi[idx].x, 2.f * c * psi[idx].y);
+  lam[idx] = Cplx<Real>::make(2 * c * psi[idx].x, 2 * c * psi[idx].y);
 }
 
-__global__ __launch_bounds__(kPgThreads) void k_pg_rot_bwd(float2* psi, float2* lam, long long amps, int q, int ref,
-                                                           int sample0, const float* csh, const float* cps, int n_ps,
-                                                           int blocks, int chunk, int slot, float* partF) {
+// Backward of one gate: the functionals Im<lambda|P|psi> (P = X, Y, Z) at the
+// cut after the gate, then psi <- u^dagger psi and lambda <- u^dagger lambda.
+template <class Real>
+__global__ __launch_bounds__(kPgThreads) void k_pg_rot_bwd(typename Cplx<Real>::T* psi, typename Cplx<Real>::T* lam,
+                                                           long long amps, int q, int ref, int sample0,
+                                                           const Real* csh, const Real* cps, int n_ps, int blocks,
+                                                           int chunk, int slot, Real* partF) {
+  using V = typename Cplx<Real>::T;
   const int s = blockIdx.x / blocks, blk = blockIdx.x - s * blocks;
-  float2* v = psi + (long long)s * amps;
-  float2* w = lam + (long long)s * amps;
-  const float* c = ref >= 0 ? csh + 8 * (long long)ref : cps + 8 * ((long long)(sample0 + s) * n_ps + (-1 - ref));
-  // u^dagger
-  const float r00 = c[0], i00 = -c[1], r01 = c[4], i01 = -c[5], r10 = c[2], i10 = -c[3], r11 = c[6], i11 = -c[7];
+  V* v = psi + (long long)s * amps;
+  V* w = lam + (long long)s * amps;
+  const Real* c = pg_coef_row(csh, cps, ref, sample0 + s, n_ps);
+  // u^dagger: transpose and conjugate
+  const Real m[8] = {c[0], -c[1], c[4], -c[5], c[2], -c[3], c[6], -c[7]};
   const long long pairs = amps >> 1;
-  float f[3] = {0, 0, 0};
+  Real f[3] = {0, 0, 0};
 #pragma unroll
   for (int k = 0; k < kPgPairsPerThread; ++k) {
     const long long p = ((long long)blk * kPgPairsPerThread + k) * kPgThreads + threadIdx.x;
     if (p >= pairs) break;
     const long long i0 = pair_lo(p, q), i1 = i0 | (1ll << q);
-    const float2 p0 = v[i0], p1 = v[i1], l0 = w[i0], l1 = w[i1];
+    V p0 = v[i0], p1 = v[i1], l0 = w[i0], l1 = w[i1];
     f[0] += l0.x * p1.y - l0.y * p1.x + l1.x * p0.y - l1.y * p0.x;
     f[1] += (l1.x * p0.x + l1.y * p0.y) - (l0.x * p1.x + l0.y * p1.y);
     f[2] += (l0.x * p0.y - l0.y * p0.x) - (l1.x * p1.y - l1.y * p1.x);
-    v[i0] = make_float2(r00 * p0.x - i00 * p0.y + r01 * p1.x - i01 * p1.y, r00 * p0.y + i00 * p0.x + r01 * p1.y + i01 * p1.x);
-    v[i1] = make_float2(r10 * p0.x - i10 * p0.y + r11 * p1.x - i11 * p1.y, r10 * p0.y + i10 * p0.x + r11 * p1.y + i11 * p1.x);
-    w[i0] = make_float2(r00 * l0.x - i00 * l0.y + r01 * l1.x - i01 * l1.y, r00 * l0.y + i00 * l0.x + r01 * l1.y + i01 * l1.x);
-    w[i1] = make_float2(r10 * l0.x - i10 * l0.y + r11 * l1.x - i11 * l1.y, r10 * l0.y + i10 * l0.x + r11 * l1.y + i11 * l1.x);
+    mat2_apply(m, p0, p1);
+    mat2_apply(m, l0, l1);
+    v[i0] = p0;
+    v[i1] = p1;
+    w[i0] = l0;
+    w[i1] = l1;
   }
   block_reduce<3>(f, partF + (((long long)s * chunk + slot) * blocks + blk) * 3, 3);
 }
 
+template <class Real>
 __global__ void k_pg_assemble(Tabs T, int r0, int cnt, int nb, int chunk, int blocks, int n_angle,
-                              const float* theta, const float* x, int F, int sample0, const float* partF, float* Gr) {
+                              const Real* theta, const Real* x, int F, int sample0, const Real* partF, Real* Gr) {
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (long long)cnt * nb) return;
   const int s = (int)(idx / cnt), i = (int)(idx - (long long)s * cnt);
@@ -265,7 +317,7 @@ struct GpuExec {
     const CoefArgs a = make_coef_args(c, d.p, th, xx, cp);
     if (coef_items(a) > 0) {
       pb();
-      hipLaunchKernelGGL(k_coef, dim3(blocks_for(coef_items(a))), dim3(kSmallThreads), 0, st, a);
+      hipLaunchKernelGGL(k_coef<float>, dim3(blocks_for(coef_items(a))), dim3(kSmallThreads), 0, st, a);
       pe(2);
       check("k_coef");
     }
@@ -293,9 +345,9 @@ struct GpuExec {
   }
 
   void reduce_E(int nb, int sample0, const float* partE, float* E) {
-    const ReduceEArgs a = make_reduce_E_args(c, nb, sample0, c.tiles * c.waves, partE, E);
+    const ReduceEArgs a = make_reduce_E_args<float>(c, nb, sample0, c.tiles * c.waves, partE, E);
     pb();
-    hipLaunchKernelGGL(k_reduce_E, dim3(blocks_for((long long)nb * c.C.K)), dim3(kSmallThreads), 0, st, a);
+    hipLaunchKernelGGL(k_reduce_E<float>, dim3(blocks_for((long long)nb * c.C.K)), dim3(kSmallThreads), 0, st, a);
     pe(2);
     check("k_reduce_E");
   }
@@ -310,78 +362,112 @@ struct GpuExec {
   }
 
   void reduce_grads(int nb, int sample0, const float* Gr, float* dtheta, float* dx, bool accumulate) {
-    const ReduceGArgs a = make_reduce_grads_args(c, d.p, nb, sample0, Gr, dtheta, dx, accumulate);
+    const ReduceGArgs a = make_reduce_grads_args<float>(c, d.p, nb, sample0, Gr, dtheta, dx, accumulate);
     const long long total = reduce_grads_items(a);
     if (total == 0) return;
     pb();
-    hipLaunchKernelGGL(k_reduce_grads, dim3(blocks_for(total)), dim3(kSmallThreads), 0, st, a);
+    hipLaunchKernelGGL(k_reduce_grads<float>, dim3(blocks_for(total)), dim3(kSmallThreads), 0, st, a);
     pe(2);
     check("k_reduce_grads");
   }
 
-  // per-gate baseline
-  void pg_init(float* psi, int nb) {
+  // per-gate kernels, in float (baseline) or double (complex128 validation)
+  template <class Real>
+  using V = typename Cplx<Real>::T;
+  template <class Real>
+  void pg_coef(const Real* th, const Real* xx, char* ws) {
+    const CoefArgsT<Real> a =
+        make_coef_args_t<Real>(c, d.p, th, xx, at<Real>(ws, c.off_coef_sh), at<Real>(ws, c.off_coef_ps));
+    if (coef_items(a) == 0) return;
     pb();
-    hipLaunchKernelGGL(k_pg_init, dim3(blocks_for(c.amps * nb)), dim3(256), 0, st, (float2*)psi, (long long)c.amps, nb);
+    hipLaunchKernelGGL(k_coef<Real>, dim3(blocks_for(coef_items(a))), dim3(kSmallThreads), 0, st, a);
+    pe(2);
+    check("k_coef");
+  }
+  template <class Real>
+  void pg_init(Real* psi, int nb) {
+    pb();
+    hipLaunchKernelGGL(k_pg_init<Real>, dim3(blocks_for(c.amps * nb)), dim3(256), 0, st, (V<Real>*)psi,
+                       (long long)c.amps, nb);
     pe(2);
     check("k_pg_init");
   }
-  void pg_copy(float* dst, const float* src, int nb) {
+  template <class Real>
+  void pg_copy(Real* dst, const Real* src, int nb) {
     if (hipMemcpyAsync(dst, src, c.state_bytes * nb, hipMemcpyDeviceToDevice, st) != hipSuccess && err == QF_OK) {
       err = QF_ERR_DEVICE;
       msg = "hipMemcpyAsync";
     }
   }
-  void pg_rot(float* psi, int nb, int sample0, int r, const float* cs, const float* cpp) {
+  template <class Real>
+  void pg_rot(Real* psi, int nb, int sample0, int r, const Real* cs, const Real* cpp) {
     pb();
-    hipLaunchKernelGGL(k_pg_rot, dim3(nb * c.pg_blocks), dim3(kPgThreads), 0, st, (float2*)psi, (long long)c.amps,
-                       c.S.runs[r].q, c.S.runs[r].coef, sample0, cs, cpp, c.S.n_coef_ps, c.pg_blocks);
+    hipLaunchKernelGGL(k_pg_rot<Real>, dim3(nb * c.pg_blocks), dim3(kPgThreads), 0, st, (V<Real>*)psi,
+                       (long long)c.amps, c.S.runs[r].q, c.S.runs[r].coef, sample0, cs, cpp, c.S.n_coef_ps,
+                       c.pg_blocks);
     pe(2);
     check("k_pg_rot");
   }
-  void pg_cz(float* psi, float* lam, int nb, int qa, int qb) {
+  template <class Real>
+  void pg_cz(Real* psi, Real* lam, int nb, int qa, int qb) {
     pb();
-    hipLaunchKernelGGL(k_pg_cz, dim3(blocks_for((c.amps >> 2) * nb)), dim3(256), 0, st, (float2*)psi, (float2*)lam,
-                       (long long)c.amps, qa, qb, nb);
+    hipLaunchKernelGGL(k_pg_cz<Real>, dim3(blocks_for((c.amps >> 2) * nb)), dim3(256), 0, st, (V<Real>*)psi,
+                       (V<Real>*)lam, (long long)c.amps, qa, qb, nb);
     pe(2);
     check("k_pg_cz");
   }
-  void pg_expect(const float* psi, int nb, float* partE) {
+  template <class Real>
+  void pg_expect(const Real* psi, int nb, Real* partE) {
     pb();
-    hipLaunchKernelGGL(k_pg_expect, dim3(nb * c.pg_blocks), dim3(kPgThreads), 0, st, (const float2*)psi,
+    hipLaunchKernelGGL(k_pg_expect<Real>, dim3(nb * c.pg_blocks), dim3(kPgThreads), 0, st, (const V<Real>*)psi,
                        (long long)c.amps, c.C.K, d.p.zmask, partE, c.pg_blocks);
     pe(2);
     check("k_pg_expect");
   }
-  void pg_reduce_E(int nb, int sample0, const float* partE, float* E) {
-    const ReduceEArgs a = make_reduce_E_args(c, nb, sample0, c.pg_blocks, partE, E);
+  template <class Real>
+  void pg_reduce_E(int nb, int sample0, const Real* partE, Real* E) {
+    const ReduceEArgsT<Real> a = make_reduce_E_args<Real>(c, nb, sample0, c.pg_blocks, partE, E);
     pb();
-    hipLaunchKernelGGL(k_reduce_E, dim3(blocks_for((long long)nb * c.C.K)), dim3(kSmallThreads), 0, st, a);
+    hipLaunchKernelGGL(k_reduce_E<Real>, dim3(blocks_for((long long)nb * c.C.K)), dim3(kSmallThreads), 0, st, a);
     pe(2);
     check("k_reduce_E");
   }
-  void pg_seed(const float* psi, float* lam, int nb, int sample0, const float* dE) {
+  template <class Real>
+  void pg_seed(const Real* psi, Real* lam, int nb, int sample0, const Real* dE) {
     pb();
-    hipLaunchKernelGGL(k_pg_seed, dim3(blocks_for(c.amps * nb)), dim3(256), 0, st, (const float2*)psi, (float2*)lam,
-                       (long long)c.amps, nb, sample0, c.C.K, d.p.zmask, dE);
+    hipLaunchKernelGGL(k_pg_seed<Real>, dim3(blocks_for(c.amps * nb)), dim3(256), 0, st, (const V<Real>*)psi,
+                       (V<Real>*)lam, (long long)c.amps, nb, sample0, c.C.K, d.p.zmask, dE);
     pe(2);
     check("k_pg_seed");
   }
-  void pg_rot_bwd(float* psi, float* lam, int nb, int sample0, int r, int slot, const float* cs, const float* cpp,
-                  float* partF) {
+  template <class Real>
+  void pg_rot_bwd(Real* psi, Real* lam, int nb, int sample0, int r, int slot, const Real* cs, const Real* cpp,
+                  Real* partF) {
     pb();
-    hipLaunchKernelGGL(k_pg_rot_bwd, dim3(nb * c.pg_blocks), dim3(kPgThreads), 0, st, (float2*)psi, (float2*)lam,
-                       (long long)c.amps, c.S.runs[r].q, c.S.runs[r].coef, sample0, cs, cpp, c.S.n_coef_ps,
-                       c.pg_blocks, c.pg_chunk, slot, partF);
+    hipLaunchKernelGGL(k_pg_rot_bwd<Real>, dim3(nb * c.pg_blocks), dim3(kPgThreads), 0, st, (V<Real>*)psi,
+                       (V<Real>*)lam, (long long)c.amps, c.S.runs[r].q, c.S.runs[r].coef, sample0, cs, cpp,
+                       c.S.n_coef_ps, c.pg_blocks, c.pg_chunk, slot, partF);
     pe(2);
     check("k_pg_rot_bwd");
   }
-  void pg_assemble(int r0, int cnt, int nb, int sample0, const float* partF, float* Gr) {
+  template <class Real>
+  void pg_assemble(int r0, int cnt, int nb, int sample0, const Real* th, const Real* xx, const Real* partF,
+                   Real* Gr) {
     pb();
-    hipLaunchKernelGGL(k_pg_assemble, dim3(blocks_for((long long)cnt * nb, 128)), dim3(128), 0, st, d.p.tabs, r0,
-                       cnt, nb, c.pg_chunk, c.pg_blocks, c.n_angle, theta, x, c.C.F, sample0, partF, Gr);
+    hipLaunchKernelGGL(k_pg_assemble<Real>, dim3(blocks_for((long long)cnt * nb, 128)), dim3(128), 0, st, d.p.tabs,
+                       r0, cnt, nb, c.pg_chunk, c.pg_blocks, c.n_angle, th, xx, c.C.F, sample0, partF, Gr);
     pe(2);
     check("k_pg_assemble");
+  }
+  template <class Real>
+  void pg_reduce_grads(int nb, int sample0, const Real* Gr, Real* dtheta, Real* dx, bool accumulate) {
+    const ReduceGArgsT<Real> a = make_reduce_grads_args<Real>(c, d.p, nb, sample0, Gr, dtheta, dx, accumulate);
+    const long long total = reduce_grads_items(a);
+    if (total == 0) return;
+    pb();
+    hipLaunchKernelGGL(k_reduce_grads<Real>, dim3(blocks_for(total)), dim3(kSmallThreads), 0, st, a);
+    pe(2);
+    check("k_reduce_grads");
   }
 };
 
@@ -460,7 +546,7 @@ qf_status qf_plan_create(const qf_circuit* circuit, int32_t batch, const qf_tuni
     T.ckpt = tuning->ckpt_interval;
     T.micro = tuning->micro_batch;
     T.store = tuning->store_ckpt;
-    if (T.mode != 0 && T.mode != 1) return fail(QF_ERR_INVALID_ARG, "mode must be 0 or 1");
+    if (T.mode < 0 || T.mode > 2) return fail(QF_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
     if (T.k < 0 || T.k > kMaxTileQubits) return fail(QF_ERR_INVALID_ARG, "tile_qubits out of range");
     if (T.R < 0 || T.R > kMaxR) return fail(QF_ERR_INVALID_ARG, "reg_qubits out of range");
     if (T.fusion < 0 || T.ckpt < 0 || T.micro < 0) return fail(QF_ERR_INVALID_ARG, "negative tuning value");
@@ -592,6 +678,7 @@ qf_status qf_forward(qf_plan* p, const float* theta, const float* x, float* E, v
   qf_status st = check_call(p, ws, ws_bytes);
   if (st != QF_OK) return st;
   const PlanCore& c = p->core;
+  if (c.c128) return fail(QF_ERR_INVALID_ARG, "complex128 plan: call qf_forward_c128");
   if (!E || (c.C.P > 0 && !theta) || (c.C.F > 0 && !x)) return fail(QF_ERR_INVALID_ARG, "NULL buffer");
   GpuExec ex(c, p->dev, (hipStream_t)stream);
   ex.prof = &p->prof;
@@ -605,6 +692,7 @@ qf_status qf_backward(qf_plan* p, const float* theta, const float* x, const floa
   qf_status st = check_call(p, ws, ws_bytes);
   if (st != QF_OK) return st;
   const PlanCore& c = p->core;
+  if (c.c128) return fail(QF_ERR_INVALID_ARG, "complex128 plan: call qf_backward_c128");
   if (!dE || (c.C.P > 0 && (!theta || !dtheta)) || (c.C.F > 0 && !x))
     return fail(QF_ERR_INVALID_ARG, "NULL buffer");
   GpuExec ex(c, p->dev, (hipStream_t)stream);
@@ -613,6 +701,35 @@ qf_status qf_backward(qf_plan* p, const float* theta, const float* x, const floa
   ex.x = x;
   ex.cp = coef_ptrs(c, (char*)ws);
   st = run_backward(c, ex, theta, x, dE, dtheta, dx, (char*)ws);
+  if (st != QF_OK) return fail(st, ex.msg);
+  return QF_OK;
+}
+
+qf_status qf_forward_c128(qf_plan* p, const double* theta, const double* x, double* E, void* ws, size_t ws_bytes,
+                          void* stream) {
+  qf_status st = check_call(p, ws, ws_bytes);
+  if (st != QF_OK) return st;
+  const PlanCore& c = p->core;
+  if (!c.c128) return fail(QF_ERR_INVALID_ARG, "plan is not a complex128 plan (tuning mode 2)");
+  if (!E || (c.C.P > 0 && !theta) || (c.C.F > 0 && !x)) return fail(QF_ERR_INVALID_ARG, "NULL buffer");
+  GpuExec ex(c, p->dev, (hipStream_t)stream);
+  ex.prof = &p->prof;
+  st = run_forward_pg<double>(c, ex, theta, x, E, (char*)ws);
+  if (st != QF_OK) return fail(st, ex.msg);
+  return QF_OK;
+}
+
+qf_status qf_backward_c128(qf_plan* p, const double* theta, const double* x, const double* dE, double* dtheta,
+                           double* dx, void* ws, size_t ws_bytes, void* stream) {
+  qf_status st = check_call(p, ws, ws_bytes);
+  if (st != QF_OK) return st;
+  const PlanCore& c = p->core;
+  if (!c.c128) return fail(QF_ERR_INVALID_ARG, "plan is not a complex128 plan (tuning mode 2)");
+  if (!dE || (c.C.P > 0 && (!theta || !dtheta)) || (c.C.F > 0 && !x))
+    return fail(QF_ERR_INVALID_ARG, "NULL buffer");
+  GpuExec ex(c, p->dev, (hipStream_t)stream);
+  ex.prof = &p->prof;
+  st = run_backward_pg<double>(c, ex, theta, x, dE, dtheta, dx, (char*)ws);
   if (st != QF_OK) return fail(st, ex.msg);
   return QF_OK;
 }

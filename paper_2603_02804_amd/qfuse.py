@@ -18,6 +18,8 @@ import torch
 from .build import LIB
 
 QF_OK = 0
+# qf_tuning.mode
+QF_MODE_FUSED, QF_MODE_PER_GATE, QF_MODE_C128 = 0, 1, 2
 _STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported", 3: "workspace too small", 4: "out of memory",
            5: "device error", 6: "internal error"}
 
@@ -93,6 +95,8 @@ def library() -> ctypes.CDLL:
             "qf_workspace_size": [P, P],
             "qf_forward": [P, P, P, P, P, SZ, P],
             "qf_backward": [P, P, P, P, P, P, P, SZ, P],
+            "qf_forward_c128": [P, P, P, P, P, SZ, P],
+            "qf_backward_c128": [P, P, P, P, P, P, P, SZ, P],
             "qf_profile_enable": [P, ctypes.c_int], "qf_profile_read": [P, P],
             "qf_batch_create": [P, P, I32, P, P], "qf_batch_destroy": [P], "qf_batch_get_info": [P, P],
             "qf_batch_workspace_size": [P, P], "qf_batch_set_launch_mode": [P, I32],
@@ -163,6 +167,17 @@ def qf_backward(plan, theta: torch.Tensor, x: Optional[torch.Tensor], dE: torch.
                                  ws_bytes, stream))
 
 
+def qf_forward_c128(plan, theta: torch.Tensor, x: Optional[torch.Tensor], E: torch.Tensor, ws: torch.Tensor,
+                    ws_bytes: int, stream) -> None:
+    _check(library().qf_forward_c128(plan, _ptr(theta), _ptr(x), _ptr(E), _ptr(ws), ws_bytes, stream))
+
+
+def qf_backward_c128(plan, theta: torch.Tensor, x: Optional[torch.Tensor], dE: torch.Tensor, dtheta: torch.Tensor,
+                     dx: Optional[torch.Tensor], ws: torch.Tensor, ws_bytes: int, stream) -> None:
+    _check(library().qf_backward_c128(plan, _ptr(theta), _ptr(x), _ptr(dE), _ptr(dtheta), _ptr(dx), _ptr(ws),
+                                      ws_bytes, stream))
+
+
 def qf_profile_enable(plan, enable: bool) -> None:
     _check(library().qf_profile_enable(plan, 1 if enable else 0))
 
@@ -212,6 +227,9 @@ class Plan:
     def __init__(self, circuit: Circuit, batch: int, tuning: Optional[qf_tuning] = None):
         self.circuit = circuit
         self.batch = int(batch)
+        # tuning mode 2: the complex128 validation path (float64 inputs and outputs)
+        self.c128 = tuning is not None and tuning.mode == QF_MODE_C128
+        self.dtype = torch.float64 if self.c128 else torch.float32
         self.handle = qf_plan_create(circuit.handle, self.batch, tuning)
         self.ws_bytes = qf_workspace_size(self.handle)
 
@@ -223,12 +241,12 @@ class Plan:
         return torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=device or "cuda")
 
     def _check_inputs(self, theta, x):
-        c = self.circuit
-        if theta.dtype != torch.float32 or not theta.is_cuda or theta.numel() != c.n_params:
-            raise ValueError("theta must be a float32 CUDA tensor of n_params elements")
+        c, dt = self.circuit, self.dtype
+        if theta.dtype != dt or not theta.is_cuda or theta.numel() != c.n_params:
+            raise ValueError(f"theta must be a {dt} CUDA tensor of n_params elements")
         if c.n_inputs:
-            if x is None or x.dtype != torch.float32 or not x.is_cuda or tuple(x.shape) != (self.batch, c.n_inputs):
-                raise ValueError("x must be a float32 CUDA tensor of shape [batch, n_inputs]")
+            if x is None or x.dtype != dt or not x.is_cuda or tuple(x.shape) != (self.batch, c.n_inputs):
+                raise ValueError(f"x must be a {dt} CUDA tensor of shape [batch, n_inputs]")
 
     def forward(self, theta: torch.Tensor, x: Optional[torch.Tensor], ws: torch.Tensor,
                 E: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -236,18 +254,20 @@ class Plan:
         theta = theta.contiguous()
         x = x.contiguous() if x is not None else None
         if E is None:
-            E = torch.empty(self.batch, self.circuit.n_obs, dtype=torch.float32, device=theta.device)
-        qf_forward(self.handle, theta, x, E, ws, ws.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            E = torch.empty(self.batch, self.circuit.n_obs, dtype=self.dtype, device=theta.device)
+        fwd = qf_forward_c128 if self.c128 else qf_forward
+        fwd(self.handle, theta, x, E, ws, ws.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         return E
 
     def backward(self, theta: torch.Tensor, x: Optional[torch.Tensor], dE: torch.Tensor, ws: torch.Tensor,
                  want_dx: bool = True):
         self._check_inputs(theta, x)
-        dE = dE.contiguous().to(torch.float32)
+        dE = dE.contiguous().to(self.dtype)
         dtheta = torch.empty_like(theta)
         dx = torch.empty_like(x) if (want_dx and x is not None) else None
-        qf_backward(self.handle, theta.contiguous(), x.contiguous() if x is not None else None, dE, dtheta, dx, ws,
-                    ws.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        bwd = qf_backward_c128 if self.c128 else qf_backward
+        bwd(self.handle, theta.contiguous(), x.contiguous() if x is not None else None, dE, dtheta, dx, ws,
+            ws.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
         return dtheta, dx
 
     def __del__(self):
@@ -263,17 +283,20 @@ class CircuitFunction(torch.autograd.Function):
     The forward keeps the plan's workspace (segment checkpoints) alive in the
     autograd context; the backward re-runs each segment from its checkpoint and
     returns dL/dtheta (summed over the batch) and dL/dx (per sample).  Inputs are
-    never modified.
+    never modified.  The workspace is released after the first backward unless
+    ``retain_workspace`` is set (needed when the graph is differentiated more
+    than once, as torch.autograd.gradcheck does).
     """
 
     @staticmethod
-    def forward(ctx, theta, x, plan: Plan):
+    def forward(ctx, theta, x, plan: Plan, retain_workspace: bool = False):
         ws = plan.new_workspace(theta.device)
         E = plan.forward(theta.detach(), x.detach() if x is not None else None, ws)
         ctx.plan = plan
         ctx.ws = ws
         ctx.save_for_backward(theta, x if x is not None else torch.empty(0, device=theta.device))
         ctx.has_x = x is not None
+        ctx.retain = bool(retain_workspace)
         return E
 
     @staticmethod
@@ -283,12 +306,14 @@ class CircuitFunction(torch.autograd.Function):
         want_dx = ctx.has_x and ctx.needs_input_grad[1]
         dtheta, dx = ctx.plan.backward(theta.detach(), x.detach() if x is not None else None, gE, ctx.ws,
                                        want_dx=want_dx)
-        ctx.ws = None
-        return dtheta, dx, None
+        if not ctx.retain:
+            ctx.ws = None
+        return dtheta, dx, None, None
 
 
-def circuit_expectations(theta: torch.Tensor, x: Optional[torch.Tensor], plan: Plan) -> torch.Tensor:
-    return CircuitFunction.apply(theta, x, plan)
+def circuit_expectations(theta: torch.Tensor, x: Optional[torch.Tensor], plan: Plan,
+                         retain_workspace: bool = False) -> torch.Tensor:
+    return CircuitFunction.apply(theta, x, plan, retain_workspace)
 
 
 # --------------------------------------------------------------------- mixed batches
