@@ -100,6 +100,13 @@ typedef struct {
   int32_t micro_batch;      /* samples per backward micro-batch                        */
   int32_t store_ckpt;       /* 1 = forward keeps segment checkpoints for the batch,
                                0 = backward re-runs the forward per micro-batch        */
+  int32_t mem_save;         /* memory-saving mode (Sec. 3.2, Sec. 3.4): 1 = the pass
+                               outputs stored inside the active checkpoint segment are
+                               kept as bfloat16 pairs (4 bytes per amplitude, rounded
+                               to nearest even) and widened on load; checkpoints and
+                               all arithmetic stay float32.  Expectations are
+                               unchanged; gradients carry the rounding of the stored
+                               states.  Fused mode only; 0 = off                       */
 } qf_tuning;
 
 /* Static description of a plan, for accounting and roofline reporting. */
@@ -108,6 +115,7 @@ typedef struct {
   int32_t fused_passes;       /* forward passes for one sample                       */
   int32_t segments;           /* checkpoint segments                                 */
   int32_t ckpt_interval, micro_batch, store_ckpt, fusion_depth;
+  int32_t mem_save;           /* stored pass outputs in bfloat16 (qf_tuning.mem_save)  */
   int64_t n_runs;             /* fused single-qubit runs                              */
   int64_t n_perm, n_u2, n_cz; /* ops per sample summed over forward passes            */
   double fwd_bytes_per_sample;   /* algorithmic HBM bytes, forward                    */

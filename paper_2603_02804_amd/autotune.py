@@ -44,19 +44,37 @@ def paper_optimal_block(stored_per_layer: float, d: int) -> float:
     return math.sqrt(d / stored_per_layer)
 
 
-def plan_states(passes: int, ckpt: int, batch: int, micro_batch: int, store: bool = True) -> int:
-    """States held by a plan's workspace: checkpoints + one segment of pass outputs + ping-pong buffers."""
+def plan_states(passes: int, ckpt: int, batch: int, micro_batch: int, store: bool = True,
+                mem_save: bool = False) -> float:
+    """States held by a plan's workspace: checkpoints + one segment of pass outputs + ping-pong buffers.
+
+    In the memory-saving mode the segment's pass outputs are bfloat16 pairs, half a state each (Sec. 3.4:
+    the stored-output coefficient of the memory model is halved)."""
     segs = -(-passes // ckpt)
     kept = batch if store else micro_batch
-    return segs * kept + max(0, ckpt - 1) * micro_batch + 4 * micro_batch
+    seg_states = max(0, ckpt - 1) * micro_batch
+    return segs * kept + (seg_states / 2 if mem_save else seg_states) + 4 * micro_batch
 
 
-def optimal_ckpt(passes: int, batch: int, micro_batch: int, store: bool = True) -> int:
+def optimal_ckpt(passes: int, batch: int, micro_batch: int, store: bool = True, mem_save: bool = False) -> int:
     kept = batch if store else micro_batch
-    guess = max(1, int(round(math.sqrt(passes * kept / max(1, micro_batch)))))
+    per = micro_batch / 2 if mem_save else micro_batch
+    guess = max(1, int(round(math.sqrt(passes * kept / max(1e-9, per)))))
     best = min(range(max(1, guess // 2), min(passes, 2 * guess) + 1),
-               key=lambda c: (plan_states(passes, c, batch, micro_batch, store), c))
+               key=lambda c: (plan_states(passes, c, batch, micro_batch, store, mem_save), c))
     return best
+
+
+def choose_storage(passes: int, batch: int, micro_batch: int, state_bytes: int, budget: float):
+    """(store_ckpt, mem_save, ckpt_interval): the first of full-precision checkpoints for the whole batch,
+    the same with bfloat16 pass outputs, per-micro-batch checkpoints, and those with bfloat16 pass
+    outputs whose workspace fits the budget (the last one when none fits)."""
+    options = ((1, 0), (1, 1), (0, 0), (0, 1))
+    for store, mem_save in options:
+        c = optimal_ckpt(passes, batch, micro_batch, bool(store), bool(mem_save))
+        if plan_states(passes, c, batch, micro_batch, bool(store), bool(mem_save)) * state_bytes <= budget:
+            return store, mem_save, c
+    return 0, 1, optimal_ckpt(passes, batch, micro_batch, False, True)
 
 
 def circuit_key(n_qubits: int, gates: np.ndarray, n_obs: int, batch: int, device: str) -> str:
@@ -152,13 +170,8 @@ def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequen
     passes = probe.info.fused_passes
     free = torch.cuda.mem_get_info()[0]
     budget = budget_bytes if budget_bytes is not None else int(0.85 * free)
-    state = 8 << n_qubits
-    store = 1
-    c = optimal_ckpt(passes, batch, out["micro_batch"], True)
-    if plan_states(passes, c, batch, out["micro_batch"], True) * state > budget:
-        store = 0
-        c = optimal_ckpt(passes, batch, out["micro_batch"], False)
-    out.update({"ckpt_interval": c, "store_ckpt": store, "candidates": results, "device": name,
+    store, mem_save, c = choose_storage(passes, batch, out["micro_batch"], 8 << n_qubits, budget)
+    out.update({"ckpt_interval": c, "store_ckpt": store, "mem_save": mem_save, "candidates": results, "device": name,
                 "passes": passes, "prefix_gates": len(pre)})
     if cache_path:
         cache = _load_cache(cache_path)
@@ -172,7 +185,8 @@ def tuning_from(d: dict):
     from . import qfuse
     return qfuse.make_tuning(tile_qubits=d.get("tile_qubits", 0), reg_qubits=d.get("reg_qubits", 0),
                              fusion_depth=d.get("fusion_depth", 0), ckpt_interval=d.get("ckpt_interval", 0),
-                             micro_batch=d.get("micro_batch", 0), store_ckpt=d.get("store_ckpt", -1))
+                             micro_batch=d.get("micro_batch", 0), store_ckpt=d.get("store_ckpt", -1),
+                             mem_save=d.get("mem_save", 0))
 
 
 def main(argv=None) -> int:

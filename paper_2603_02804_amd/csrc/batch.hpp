@@ -242,13 +242,14 @@ inline bool check_pass_job(const PassJob& j, const PlanCore& c, uint32_t blocks,
   const uint64_t nb = blocks >> S.tiles_log2;
   if (nb == 0 || ((uint64_t)nb << S.tiles_log2) != blocks) return false;
   const uint64_t amps = uint64_t(1) << c.C.n;
-  auto state_ext = [&](long long stride) { return ((nb - 1) * (uint64_t)stride + amps) * 8; };
+  auto state_ext = [&](long long stride, int bf16) { return ((nb - 1) * (uint64_t)stride + amps) * (bf16 ? 4 : 8); };
   if (j.pass < 0 || j.pass >= (int)S.passes.size()) return false;
   const uint64_t ns = (uint64_t)S.passes[j.pass].n_slots;
   bool ok = true;
-  ok &= in_region(A.src0, state_ext(A.s0), r);
-  ok &= in_region(A.src1, state_ext(A.s1), r);
-  ok &= in_region(A.dst, state_ext(A.sd), r);
+  ok &= in_region(A.src0, state_ext(A.s0, A.src0_bf16), r);
+  ok &= in_region(A.src1, state_ext(A.s1, 0), r);
+  ok &= in_region(A.dst, state_ext(A.sd, 0), r);
+  ok &= in_region(A.dst2, state_ext(A.sd2, 1), r);
   ok &= in_region(A.partF, nb * c.tiles * 3 * ns * 4, r);
   ok &= in_region(A.partE, nb * c.tiles * (uint64_t)c.waves * c.C.K * 4, r);
   ok &= in_region(A.coef_sh, 32ull * std::max(1, S.n_coef_shared), r);

@@ -181,13 +181,13 @@ __device__ __forceinline__ void scale_all(float2 (&a)[NA], float2 p) {
 
 template <int NA>
 __device__ __forceinline__ void flip_signs(float2 (&a)[NA], uint32_t sign) {
+  // negation of slot jj where bit jj of sign is set, as an XOR of the float
+  // sign bits (exact; no compare or select)
 #pragma unroll
-  // multiplications by +-1 (exact); float arithmetic only, so that the array
-  // never mixes float and integer accesses and stays in registers
   for (int jj = 0; jj < NA; ++jj) {
-    const float g = ((sign >> jj) & 1u) ? -1.f : 1.f;
-    a[jj].x *= g;
-    a[jj].y *= g;
+    const uint32_t m = (sign << (31 - jj)) & 0x80000000u;
+    a[jj].x = __uint_as_float(__float_as_uint(a[jj].x) ^ m);
+    a[jj].y = __uint_as_float(__float_as_uint(a[jj].y) ^ m);
   }
 }
 
@@ -239,6 +239,19 @@ __device__ __forceinline__ const float* run_coef(const KArgs& A, int ref, int sa
 __device__ __forceinline__ float2 event_coef(const KArgs& A, int ref, int sample) {
   const float* p = ref >= 0 ? A.ev_sh + 2 * (size_t)ref : A.ev_ps + 2 * ((size_t)sample * A.n_evps + (-1 - ref));
   return make_float2(cld(p), cld(p + 1));
+}
+
+// Memory-saving storage of an amplitude: real and imaginary parts as two
+// bfloat16 in one word (round to nearest even, real part in the low half), and
+// the exact widening back to float.
+typedef __bf16 qf_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float qf_f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float2 v) {
+  const qf_f32x2 f = {v.x, v.y};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f, qf_bf16x2));
+}
+__device__ __forceinline__ float2 widen_bf16x2(uint32_t u) {
+  return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
 }
 
 // LDS amplitude at a byte offset (layouts hold LDS positions in bytes).
@@ -481,7 +494,11 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         // every lane loads: the thread tables are zero above the tile's thread
         // bits, so lanes beyond the tile read (and later drop) in-tile elements;
         // an unpredicated load keeps the register arrays in place
-        if (op.b == 0) {
+        if (op.b == 0 && A.src0_bf16) {
+          const uint32_t* src = reinterpret_cast<const uint32_t*>(A.src0) + (long long)sl * A.s0;
+#pragma unroll
+          for (int jj = 0; jj < NA; ++jj) a[jj] = widen_bf16x2(src[base | rb(jj)]);
+        } else if (op.b == 0) {
           const float2* src = reinterpret_cast<const float2*>(A.src0) + (long long)sl * A.s0;
 #pragma unroll
           for (int jj = 0; jj < NA; ++jj) a[jj] = src[base | rb(jj)];
@@ -509,6 +526,11 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
           } else {
 #pragma unroll
             for (int jj = 0; jj < NA; ++jj) dst[base | rb(jj)] = a[jj];
+            if (A.dst2) {
+              uint32_t* dst2 = A.dst2 + (long long)sl * A.sd2;
+#pragma unroll
+              for (int jj = 0; jj < NA; ++jj) dst2[base | rb(jj)] = pack_bf16x2(a[jj]);
+            }
           }
         }
         break;

@@ -30,6 +30,10 @@ struct PassLaunch {
   const float* src0 = nullptr; int64_t src0_stride = 0;   // psi input  (interleaved complex)
   const float* src1 = nullptr; int64_t src1_stride = 0;   // lambda input
   float* dst = nullptr; int64_t dst_stride = 0;           // psi (fwd) or lambda (bwd) output
+  // memory-saving mode: strides count 4-byte words (2 per complex64 amplitude,
+  // 1 per bfloat16 pair)
+  bool src0_bf16 = false;   // psi input stored as bfloat16 pairs
+  uint32_t* dst2 = nullptr; int64_t dst2_stride = 0;      // forward: bfloat16 copy of the output
   float* partF = nullptr;   // backward functional partial sums of this pass: [sample][tile][slot][3]
   float* partE = nullptr;   // forward expectation partial sums
   const float* dE = nullptr;
@@ -44,6 +48,7 @@ struct PlanCore {
   bool per_gate = false;              // one kernel per gate (float baseline or complex128)
   bool c128 = false;                  // complex128 validation path (double throughout)
   int P = 0, ckpt = 1, n_seg = 1, mb = 1, store = 1;
+  int memsave = 0;                    // stored pass outputs of the active segment in bfloat16
   int waves = 1, tiles = 1;
   int64_t amps = 1;                   // 2^n
   size_t state_bytes = 8;
@@ -152,6 +157,7 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
     c.mb = std::max(1, std::min(m, B));
   }
   c.store = T.store >= 0 ? (T.store ? 1 : 0) : 1;
+  c.memsave = T.memsave ? 1 : 0;
   // partial-sum offsets per pass, relative to the segment start
   c.partF_off.assign(c.P, 0);
   for (int s = 0; s < c.n_seg; ++s) {
@@ -183,7 +189,7 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
   c.off_ev_ps = off;   off = align_up(off + sizeof(float) * 2 * std::max<int64_t>(1, int64_t(B) * S.n_ev_ps));
   c.off_ckpt = off;    off = align_up(off + SB * size_t(nck) * c.n_seg);
   c.off_work = off;    off = align_up(off + SB * size_t(c.mb) * 2);
-  c.off_seg = off;     off = align_up(off + SB * size_t(c.mb) * std::max(0, c.ckpt - 1));
+  c.off_seg = off;     off = align_up(off + (c.memsave ? SB / 2 : SB) * size_t(c.mb) * std::max(0, c.ckpt - 1));
   c.off_lam = off;     off = align_up(off + SB * size_t(c.mb) * 2);
   c.off_partE = off;   off = align_up(off + sizeof(float) * std::max<int64_t>(1, int64_t(c.mb) * c.tiles * c.waves * C.K));
   c.off_partF = off;   off = align_up(off + sizeof(float) * std::max<int64_t>(1, int64_t(c.mb) * c.partF_seg_floats));
@@ -310,7 +316,10 @@ template <class Exec>
 qf_status run_backward_fused(const PlanCore& c, Exec& ex, const float* theta, const float* x, const float* dE,
                              float* dtheta, float* dx, char* ws) {
   const int64_t SA = 2 * c.amps;
+  const int64_t SS = c.memsave ? c.amps : SA;   // words per stored pass output
+  const bool bf = c.memsave != 0;
   float* seg = at<float>(ws, c.off_seg);
+  float* work = at<float>(ws, c.off_work);
   float* lam = at<float>(ws, c.off_lam);
   float* partF = at<float>(ws, c.off_partF);
   float* Gr = at<float>(ws, c.off_Gr);
@@ -330,12 +339,24 @@ qf_status run_backward_fused(const PlanCore& c, Exec& ex, const float* theta, co
         L.sample0 = mb0;
         if (p == a) {
           if (s > 0) { L.src0 = ck + (s - 1) * SA; L.src0_stride = ck_stride; }
+        } else if (bf) {
+          // the recompute continues from the float32 output of the previous pass
+          L.src0 = work + ((p - 1) & 1) * SA * nb;
+          L.src0_stride = SA;
         } else {
           L.src0 = seg + int64_t(p - 1 - a) * SA;
           L.src0_stride = SA * (c.ckpt - 1);
         }
-        L.dst = seg + int64_t(p - a) * SA;
-        L.dst_stride = SA * (c.ckpt - 1);
+        if (bf) {
+          // float32 output for the next recompute pass, bfloat16 copy kept for the adjoint pass
+          L.dst = work + (p & 1) * SA * nb;
+          L.dst_stride = SA;
+          L.dst2 = reinterpret_cast<uint32_t*>(seg) + int64_t(p - a) * SS;
+          L.dst2_stride = SS * (c.ckpt - 1);
+        } else {
+          L.dst = seg + int64_t(p - a) * SA;
+          L.dst_stride = SA * (c.ckpt - 1);
+        }
         ex.pass(L);
       }
       // fused adjoint passes
@@ -346,7 +367,7 @@ qf_status run_backward_fused(const PlanCore& c, Exec& ex, const float* theta, co
         L.nb = nb;
         L.sample0 = mb0;
         if (p == b - 1) { L.src0 = ck + s * SA; L.src0_stride = ck_stride; }
-        else { L.src0 = seg + int64_t(p - a) * SA; L.src0_stride = SA * (c.ckpt - 1); }
+        else { L.src0 = seg + int64_t(p - a) * SS; L.src0_stride = SS * (c.ckpt - 1); L.src0_bf16 = bf; }
         if (p != c.P - 1) { L.src1 = lam + li * SA * nb; L.src1_stride = SA; }
         if (p > 0) { L.dst = lam + (1 - li) * SA * nb; L.dst_stride = SA; }
         L.partF = partF + int64_t(nb) * c.partF_off[p];

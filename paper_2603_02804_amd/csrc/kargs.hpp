@@ -78,6 +78,9 @@ struct KArgs {
   int tb;                     // thread bits of the tile
   int do_expect;
   int tile_elems;             // 2^k: LDS elements of the tile; wave partial sums follow
+  uint32_t* dst2;             // forward: bfloat16-pair copy of the output (memory-saving mode)
+  long long sd2;              // its per-sample stride (words)
+  int src0_bf16;              // psi input as bfloat16 pairs (4 bytes per amplitude)
 };
 
 // Workspace addresses of the coefficient tables of one call.
@@ -119,11 +122,14 @@ inline KArgs make_pass_args(const PlanCore& c, const PlanPtrs& d, const CoefPtrs
   A.n_ps = S.n_coef_ps;
   A.n_evps = S.n_ev_ps;
   A.src0 = L.src0;
-  A.s0 = L.src0_stride / 2;
+  A.s0 = L.src0_bf16 ? L.src0_stride : L.src0_stride / 2;
+  A.src0_bf16 = L.src0_bf16 ? 1 : 0;
   A.src1 = L.src1;
   A.s1 = L.src1_stride / 2;
   A.dst = L.dst;
   A.sd = L.dst_stride / 2;
+  A.dst2 = L.dst2;
+  A.sd2 = L.dst2_stride;
   A.partF = L.partF;
   A.partE = L.partE;
   A.dE = L.dE;

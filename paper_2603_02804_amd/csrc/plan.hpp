@@ -36,6 +36,7 @@ struct Tuning {
   int ckpt = 0;          // passes per checkpoint segment
   int micro = 0;         // samples per micro-batch
   int store = -1;        // keep checkpoints of the whole batch in the forward
+  int memsave = 0;       // stored pass outputs of the active segment as bfloat16 pairs
 };
 
 struct Schedule {

@@ -21,6 +21,22 @@
 namespace qf {
 namespace {
 
+// bfloat16 storage of the memory-saving mode: round to nearest even (NaN kept
+// quiet) and the exact widening.
+inline uint16_t bf16_round(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+inline float bf16_widen(uint16_t h) {
+  const uint32_t u = uint32_t(h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
 using cd = std::complex<double>;
 
 struct M2 {
@@ -246,13 +262,20 @@ struct CpuExec {
               const int64_t stride = op.b == 0 ? L.src0_stride : L.src1_stride;
               std::vector<CF>& v = op.b == 0 ? a : l;
               const uint32_t tm = op.c ? tout : tin;
+              const bool bf = op.b == 0 && L.src0_bf16;
               for (int t = 0; t < active; ++t)
                 for (int jj = 0; jj < NA; ++jj) {
                   uint64_t idx = tm | tbase(Ly.mem_thr, t) | reg_index(Ly.mem_reg, jj);
                   if (idx >= (uint64_t)c.amps) oob("load index");
-                  const float* p = src + sl * stride + 2 * idx;
-                  in_ws(p, 8, "load address");
-                  v[t * NA + jj] = CF{p[0], p[1]};
+                  if (bf) {
+                    const uint32_t* p = reinterpret_cast<const uint32_t*>(src) + sl * stride + idx;
+                    in_ws(p, 4, "load address");
+                    v[t * NA + jj] = CF{bf16_widen(uint16_t(*p & 0xffffu)), bf16_widen(uint16_t(*p >> 16))};
+                  } else {
+                    const float* p = src + sl * stride + 2 * idx;
+                    in_ws(p, 8, "load address");
+                    v[t * NA + jj] = CF{p[0], p[1]};
+                  }
                 }
               break;
             }
@@ -266,6 +289,11 @@ struct CpuExec {
                 for (int jj = 0; jj < NA; ++jj) {
                   uint64_t idx = tm | tbase(Ly.mem_thr, t) | reg_index(Ly.mem_reg, jj);
                   if (idx >= (uint64_t)c.amps) oob("store index");
+                  if (!L.bwd && L.dst2) {
+                    uint32_t* q = L.dst2 + sl * L.dst2_stride + idx;
+                    in_ws(q, 4, "store address");
+                    *q = uint32_t(bf16_round(v[t * NA + jj].re)) | (uint32_t(bf16_round(v[t * NA + jj].im)) << 16);
+                  }
                   float* p = L.dst + sl * L.dst_stride + 2 * idx;
                   in_ws(p, 8, "store address");
                   p[0] = v[t * NA + jj].re;
@@ -678,7 +706,7 @@ int qfc_run(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tuning,
     Tuning T;
     if (tuning) {
       T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
-      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt;
+      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save;
     }
     if (T.mode == 2) { g_err = "the checker runs float plans only"; return QF_ERR_UNSUPPORTED; }
     PlanCore pc;
@@ -710,7 +738,7 @@ int qfc_stats(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tunin
   Tuning T;
   if (tuning) {
     T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
-    T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt;
+    T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save;
   }
   PlanCore pc;
   st = build_plan_core(C, batch, T, &pc, &msg);
@@ -736,7 +764,7 @@ int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, i
     Tuning T;
     if (tuning) {
       T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
-      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt;
+      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save;
     }
     std::vector<std::unique_ptr<PlanCore>> pcs;
     std::vector<const PlanCore*> cores;
@@ -792,6 +820,7 @@ int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, i
             pl.src0 = rb(pl.src0);
             pl.src1 = rb(pl.src1);
             pl.dst = rb(pl.dst);
+            pl.dst2 = rb(pl.dst2);
             pl.partF = rb(pl.partF);
             pl.partE = rb(pl.partE);
             pl.dE = dE ? dE[j.circ] : nullptr;

@@ -546,10 +546,13 @@ qf_status qf_plan_create(const qf_circuit* circuit, int32_t batch, const qf_tuni
     T.ckpt = tuning->ckpt_interval;
     T.micro = tuning->micro_batch;
     T.store = tuning->store_ckpt;
+    T.memsave = tuning->mem_save;
     if (T.mode < 0 || T.mode > 2) return fail(QF_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
     if (T.k < 0 || T.k > kMaxTileQubits) return fail(QF_ERR_INVALID_ARG, "tile_qubits out of range");
     if (T.R < 0 || T.R > kMaxR) return fail(QF_ERR_INVALID_ARG, "reg_qubits out of range");
     if (T.fusion < 0 || T.ckpt < 0 || T.micro < 0) return fail(QF_ERR_INVALID_ARG, "negative tuning value");
+    if (T.memsave != 0 && T.memsave != 1) return fail(QF_ERR_INVALID_ARG, "mem_save must be 0 or 1");
+    if (T.memsave && T.mode != 0) return fail(QF_ERR_INVALID_ARG, "mem_save applies to the fused mode only");
   }
   qf_plan* p = nullptr;
   try {
@@ -622,6 +625,7 @@ qf_status qf_plan_get_info(const qf_plan* p, qf_plan_info* info) {
   info->ckpt_interval = c.ckpt;
   info->micro_batch = c.mb;
   info->store_ckpt = c.store;
+  info->mem_save = c.memsave;
   info->fusion_depth = S.fusion;
   info->n_perm = S.n_perm;
   info->n_u2 = S.n_u2;
@@ -630,14 +634,19 @@ qf_status qf_plan_get_info(const qf_plan* p, qf_plan_info* info) {
   // state once; an adjoint pass reads psi and lambda and writes lambda
   const double P = c.P;
   info->fwd_bytes_per_sample = (2 * P - 1) * SB;
-  int64_t recompute = 0;
+  // stored pass outputs of the active segment: half size in the memory-saving
+  // mode, where a recompute pass writes its float32 output for the next pass
+  // and a bfloat16 copy for the adjoint pass
+  const double ST = c.memsave ? 0.5 * SB : SB;
+  double recompute = 0, adj = 0;
   for (int s = 0; s < c.n_seg; ++s) {
     const int a = c.seg_begin[s], b = c.seg_begin[s + 1];
-    for (int q = a; q <= b - 2; ++q) recompute += (q == 0) ? 1 : 2;
+    for (int q = a; q <= b - 2; ++q) recompute += (q == 0 ? 0 : SB) + SB + (c.memsave ? ST : 0);
+    for (int q = a; q < b; ++q)   // psi_out, lambda_out (none for the seed pass), lambda_in (none for pass 0)
+      adj += (q == b - 1 ? SB : ST) + (q == c.P - 1 ? 0 : SB) + (q == 0 ? 0 : SB);
   }
-  const double adj = 3 * P - 2;   // the seed pass reads no lambda, pass 0 writes none
-  info->bwd_pass_bytes_per_sample = adj * SB;
-  info->bwd_bytes_per_sample = (recompute + adj) * SB + (c.store ? 0 : info->fwd_bytes_per_sample);
+  info->bwd_pass_bytes_per_sample = adj;
+  info->bwd_bytes_per_sample = recompute + adj + (c.store ? 0 : info->fwd_bytes_per_sample);
   // algorithmic flops of a run, per amplitude, in the method's terms (one
   // fused 2x2 complex matrix per run): forward and recompute apply it (8
   // multiply-adds, 16 flops); the adjoint pass un-applies it from psi and

@@ -35,3 +35,35 @@ def test_optimal_ckpt_brute_force():
         c = autotune.optimal_ckpt(passes, batch, mb, store)
         brute = min(autotune.plan_states(passes, k, batch, mb, store) for k in range(1, passes + 1))
         assert autotune.plan_states(passes, c, batch, mb, store) == brute
+
+
+def test_optimal_ckpt_brute_force_mem_save():
+    for passes, batch, mb, store in [(249, 1000, 32, True), (249, 1000, 32, False), (26, 64, 8, True)]:
+        c = autotune.optimal_ckpt(passes, batch, mb, store, True)
+        brute = min(autotune.plan_states(passes, k, batch, mb, store, True) for k in range(1, passes + 1))
+        assert autotune.plan_states(passes, c, batch, mb, store, True) == brute
+
+
+def test_mem_save_halves_stored_outputs_only():
+    # checkpoints and ping-pong states stay full size; the segment's stored outputs halve
+    full = autotune.plan_states(100, 10, 64, 8, True, False)
+    half = autotune.plan_states(100, 10, 64, 8, True, True)
+    assert full - half == 9 * 8 / 2
+
+
+def test_choose_storage_order():
+    S = 8 << 20
+    P, B, mb = 249, 1000, 32
+    c1 = autotune.optimal_ckpt(P, B, mb, True, False)
+    need_full = autotune.plan_states(P, c1, B, mb, True, False) * S
+    assert autotune.choose_storage(P, B, mb, S, need_full)[:2] == (1, 0)
+    c2 = autotune.optimal_ckpt(P, B, mb, True, True)
+    need_half = autotune.plan_states(P, c2, B, mb, True, True) * S
+    assert need_half < need_full
+    assert autotune.choose_storage(P, B, mb, S, need_half)[:2] == (1, 1)
+    assert autotune.choose_storage(P, B, mb, S, 1)[:2] == (0, 1)
+
+
+def test_tuning_from_mem_save():
+    t = autotune.tuning_from({"tile_qubits": 12, "mem_save": 1})
+    assert t.mem_save == 1 and t.mode == 0

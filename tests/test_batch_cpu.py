@@ -23,6 +23,7 @@ def _dEs(ws, seed):
     dict(n=6, qubits=(3, 9), layers=(1, 6), samples=3, seed=11, tuning={}),
     dict(n=5, qubits=(11, 14), layers=(2, 5), samples=2, seed=12, tuning=dict(fusion_depth=2, ckpt_interval=2)),
     dict(n=4, qubits=(12, 13), layers=(3, 6), samples=5, seed=13, tuning=dict(micro_batch=2, ckpt_interval=3)),
+    dict(n=4, qubits=(12, 14), layers=(4, 8), samples=3, seed=14, tuning=dict(ckpt_interval=2, mem_save=1)),
 ])
 def test_batch_replay_equals_single(case):
     ws = mixed(case["n"], case["qubits"], case["layers"], case["samples"], case["seed"])
