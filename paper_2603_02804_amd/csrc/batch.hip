@@ -269,6 +269,11 @@ qf_status qf_batch_create(const qf_circuit* const* circuits, const int32_t* samp
       return set_error(st, m);
     }
     b->plans.push_back(p);
+    if (p->core.S.general_obs) {
+      destroy_batch(b);
+      return set_error(QF_ERR_UNSUPPORTED, "circuit " + std::to_string(i) +
+                                               ": mixed batches take Z-string observables only");
+    }
   }
   std::string msg;
   qf_status st = QF_OK;

@@ -100,6 +100,11 @@ struct RecordExec {
     out.pblocks.push_back(pass_blocks(c, L.nb));
     out.pshmem.push_back((uint32_t)pass_shmem(c, L.bwd));
   }
+  // circuits with X / Y observables are rejected at batch creation
+  void pauli_expect(const float*, int64_t, int, float*) { failed = true; }
+  void pauli_reduce_E(int, int, const float*, float*) { failed = true; }
+  void pauli_seed(const float*, int64_t, float*, int64_t, int, int, const float*) { failed = true; }
+  bool failed = false;
   void reduce_E(int nb, int sample0, const float* partE, float*) {
     SmallJob j = job(SJ_REDUCE_E, circ);
     j.u.re = make_reduce_E_args<float>(c, nb, sample0, c.tiles * c.waves, partE, nullptr);

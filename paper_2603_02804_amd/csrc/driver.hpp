@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "plan.hpp"
@@ -62,6 +63,7 @@ struct PlanCore {
   // per-gate baseline
   int pg_chunk = 0;                   // rotation gates per partial-sum chunk
   int pg_blocks = 0;                  // partial sums per sample per gate
+  int pauli_blocks = 1;               // partial sums per sample of the Pauli-string expectation
   // workspace
   size_t off_coef_sh = 0, off_coef_ps = 0, off_ev_sh = 0, off_ev_ps = 0;
   size_t off_ckpt = 0, off_work = 0, off_seg = 0, off_lam = 0;
@@ -71,6 +73,8 @@ struct PlanCore {
 // Shape of one per-gate kernel launch: pairs per thread and threads per block.
 constexpr int kPgThreads = 256;
 constexpr int kPgPairsPerThread = 4;
+// Amplitudes per thread of the Pauli-string expectation kernel.
+constexpr int kPauliAmpsPerThread = 8;
 
 inline void build_csr(int n_keys, const std::vector<std::pair<int, int>>& kv, std::vector<int32_t>* begin,
                       std::vector<int32_t>* vals) {
@@ -116,6 +120,8 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
   build_csr(C.F, in, &c.in_ref_begin, &c.in_refs);
 
   const size_t SB = c.state_bytes;
+  c.pauli_blocks = (int)std::max<int64_t>(1, (c.amps + int64_t(kPgThreads) * kPauliAmpsPerThread - 1) /
+                                                  (int64_t(kPgThreads) * kPauliAmpsPerThread));
   if (c.per_gate) {
     c.mb = T.micro > 0 ? std::min(T.micro, B) : std::min(B, 8);
     const int64_t pairs = std::max<int64_t>(1, c.amps / 2);
@@ -130,7 +136,7 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
     c.off_ev_ps = off;   off = align_up(off + rb * 2);
     c.off_ckpt = off;    off = align_up(off + SB * B);            // final states of the batch
     c.off_lam = off;     off = align_up(off + SB * 2 * c.mb);     // psi copy + lambda
-    c.off_partE = off;   off = align_up(off + rb * std::max<int64_t>(1, int64_t(c.mb) * c.pg_blocks * C.K));
+    c.off_partE = off;   off = align_up(off + rb * std::max<int64_t>(1, int64_t(c.mb) * c.pauli_blocks * C.K));
     c.off_partF = off;   off = align_up(off + rb * int64_t(c.mb) * c.pg_chunk * c.pg_blocks * 3);
     c.off_Gr = off;      off = align_up(off + rb * std::max<int64_t>(1, int64_t(c.mb) * c.n_angle));
     c.ws_bytes = off;
@@ -191,11 +197,30 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
   c.off_work = off;    off = align_up(off + SB * size_t(c.mb) * 2);
   c.off_seg = off;     off = align_up(off + (c.memsave ? SB / 2 : SB) * size_t(c.mb) * std::max(0, c.ckpt - 1));
   c.off_lam = off;     off = align_up(off + SB * size_t(c.mb) * 2);
-  c.off_partE = off;   off = align_up(off + sizeof(float) * std::max<int64_t>(1, int64_t(c.mb) * c.tiles * c.waves * C.K));
+  c.off_partE = off;   off = align_up(off + sizeof(float) * std::max<int64_t>(1, int64_t(c.mb) * C.K *
+                                                                             (S.general_obs ? c.pauli_blocks : c.tiles * c.waves)));
   c.off_partF = off;   off = align_up(off + sizeof(float) * std::max<int64_t>(1, int64_t(c.mb) * c.partF_seg_floats));
   c.off_Gr = off;      off = align_up(off + sizeof(float) * std::max<int64_t>(1, int64_t(c.mb) * c.n_angle));
   c.ws_bytes = off;
   return QF_OK;
+}
+
+// The observables as Pauli records in the bit order of the state they are
+// applied to: logical for the per-gate paths, the last pass's output order for
+// the fused path.
+inline std::vector<PauliRec> pauli_table(const PlanCore& c) {
+  std::vector<PauliRec> out;
+  for (const qf_pauli& o : c.C.obs) {
+    PauliRec r{0, 0, 0, 0};
+    for (int q = 0; q < c.C.n; ++q) {
+      const int m = (!c.per_gate && !c.S.final_map.empty()) ? c.S.final_map[q] : q;
+      if ((o.x_mask >> q) & 1) r.xm |= 1u << m;
+      if ((o.z_mask >> q) & 1) r.zm |= 1u << m;
+    }
+    r.ny = __builtin_popcountll(o.x_mask & o.z_mask) & 3;
+    out.push_back(r);
+  }
+  return out;
 }
 
 template <class T>
@@ -225,8 +250,8 @@ qf_status run_forward_pg(const PlanCore& c, Exec& ex, const Real* theta, const R
       if (g.kind == QF_CZ) ex.pg_cz(psi, (Real*)nullptr, nb, g.q0, g.q1);
       else ex.pg_rot(psi, nb, mb0, r++, csh, cps);
     }
-    ex.pg_expect((const Real*)psi, nb, at<Real>(ws, c.off_partE));
-    ex.pg_reduce_E(nb, mb0, (const Real*)at<Real>(ws, c.off_partE), E);
+    ex.pauli_expect((const Real*)psi, SA, nb, at<Real>(ws, c.off_partE));
+    ex.pauli_reduce_E(nb, mb0, (const Real*)at<Real>(ws, c.off_partE), E);
   }
   return ex.status();
 }
@@ -246,7 +271,7 @@ qf_status run_backward_pg(const PlanCore& c, Exec& ex, const Real* theta, const 
     Real* psi = at<Real>(ws, c.off_lam);
     Real* lam = psi + SA * nb;
     ex.pg_copy(psi, fin, nb);
-    ex.pg_seed((const Real*)psi, lam, nb, mb0, dE);
+    ex.pauli_seed((const Real*)psi, SA, lam, SA, nb, mb0, dE);
     int r = nrot;
     for (int64_t j = (int64_t)c.C.gates.size() - 1; j >= 0; --j) {
       const qf_gate& g = c.C.gates[j];
@@ -267,9 +292,11 @@ qf_status run_backward_pg(const PlanCore& c, Exec& ex, const Real* theta, const 
 }
 
 // ---------------------------------------------------------------- fused path
+// Runs the forward passes of one micro-batch; returns the final state and its
+// per-sample stride (floats).
 template <class Exec>
-void forward_passes(const PlanCore& c, Exec& ex, char* ws, int mb0, int nb, bool keep_ckpt, float* ckpt_base,
-                    bool do_expect) {
+std::pair<const float*, int64_t> forward_passes(const PlanCore& c, Exec& ex, char* ws, int mb0, int nb,
+                                                bool keep_ckpt, float* ckpt_base, bool do_expect) {
   const int64_t SA = 2 * c.amps;   // floats per state
   float* work = at<float>(ws, c.off_work);
   float* partE = at<float>(ws, c.off_partE);
@@ -297,6 +324,7 @@ void forward_passes(const PlanCore& c, Exec& ex, char* ws, int mb0, int nb, bool
     src = L.dst;
     src_stride = L.dst_stride;
   }
+  return {src, src_stride};
 }
 
 template <class Exec>
@@ -306,8 +334,14 @@ qf_status run_forward_fused(const PlanCore& c, Exec& ex, const float* theta, con
   for (int mb0 = 0; mb0 < c.B; mb0 += c.mb) {
     const int nb = std::min(c.mb, c.B - mb0);
     float* ck = at<float>(ws, c.off_ckpt) + (c.store ? int64_t(mb0) * c.n_seg * SA : 0);
-    forward_passes(c, ex, ws, mb0, nb, c.store != 0, ck, true);
-    ex.reduce_E(nb, mb0, at<float>(ws, c.off_partE), E);
+    const auto fin = forward_passes(c, ex, ws, mb0, nb, c.store != 0, ck, true);
+    if (c.S.general_obs) {
+      // X / Y observables: from the stored output state, in its bit order
+      ex.pauli_expect(fin.first, fin.second, nb, at<float>(ws, c.off_partE));
+      ex.pauli_reduce_E(nb, mb0, (const float*)at<float>(ws, c.off_partE), E);
+    } else {
+      ex.reduce_E(nb, mb0, at<float>(ws, c.off_partE), E);
+    }
   }
   return ex.status();
 }
@@ -368,7 +402,9 @@ qf_status run_backward_fused(const PlanCore& c, Exec& ex, const float* theta, co
         L.sample0 = mb0;
         if (p == b - 1) { L.src0 = ck + s * SA; L.src0_stride = ck_stride; }
         else { L.src0 = seg + int64_t(p - a) * SS; L.src0_stride = SS * (c.ckpt - 1); L.src0_bf16 = bf; }
-        if (p != c.P - 1) { L.src1 = lam + li * SA * nb; L.src1_stride = SA; }
+        if (p == c.P - 1 && c.S.general_obs)   // seed from the stored output state
+          ex.pauli_seed((const float*)(ck + s * SA), ck_stride, lam + li * SA * nb, SA, nb, mb0, dE);
+        if (p != c.P - 1 || c.S.general_obs) { L.src1 = lam + li * SA * nb; L.src1_stride = SA; }
         if (p > 0) { L.dst = lam + (1 - li) * SA * nb; L.dst_stride = SA; }
         L.partF = partF + int64_t(nb) * c.partF_off[p];
         L.dE = dE;

@@ -42,6 +42,7 @@ struct PlanPtrs {
   const uint32_t* zmask = nullptr;
   const PhaseEv* pev = nullptr;
   const CzaRec* cza = nullptr;
+  const PauliRec* pauli = nullptr;   // observables in the final state's bit order
   Tabs tabs{};
 };
 

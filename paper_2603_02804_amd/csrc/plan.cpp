@@ -44,8 +44,6 @@ qf_status validate_circuit(const qf_circuit_desc* d, std::string* msg) {
     const uint64_t lim = (n == 64) ? ~0ull : ((1ull << n) - 1);
     if ((d->obs[k].x_mask | d->obs[k].z_mask) & ~lim)
       return fail(QF_ERR_INVALID_ARG, "observable acts outside the register");
-    if (d->obs[k].x_mask != 0)
-      return fail(QF_ERR_UNSUPPORTED, "only Z-string observables (x_mask == 0) are implemented");
   }
   return QF_OK;
 }
@@ -358,6 +356,7 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
   Schedule& S = *Sp;
   S = Schedule{};
   const int n = C.n;
+  for (const qf_pauli& o : C.obs) S.general_obs = S.general_obs || o.x_mask != 0;
   // default tile: 2^12 amplitudes, 4 register qubits per lane, 256 lanes; the
   // adjoint kernel then holds psi and lambda in 64 VGPRs and keeps 3 waves per SIMD
   const int k = std::min(n, T.k > 0 ? std::min(T.k, kMaxTileQubits) : kDefaultTileQubits);
@@ -596,6 +595,44 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
       for (auto& e : evs) S.pev.push_back(e);
       S.ops.push_back({OP_DIAGT, cur, cb, (int)gs.size(), eb, (int)evs.size(), 0, 0});
     };
+    // diagonal items touching register bits: phases per register bit (PHASEA),
+    // CZ signs per amplitude (one CZA for all edges)
+    auto apply_amp = [&](const std::vector<int>& ids) {
+      std::vector<std::pair<int, int>> edges;
+      for (int id : ids) {
+        Item& it = items[id];
+        if (it.applied) continue;
+        it.applied = true;
+        S.n_diag_amp++;
+        if (it.kind == 1) {
+          edges.push_back({it.q0, it.q1});
+        } else {
+          int j = (int)(std::find(regq.begin(), regq.end(), it.q0) - regq.begin());
+          const int eb = (int)S.pev.size();
+          S.pev.push_back(S.pev[it.ev]);
+          S.ops.push_back({OP_PHASEA, j, eb, 0, 0, 0, 0, 0});
+        }
+      }
+      if (edges.empty()) return;
+      CzaRec cr;
+      std::memset(&cr, 0, sizeof(cr));
+      std::vector<int> rb(n, -1);
+      for (int j = 0; j < R; ++j) rb[regq[j]] = j;
+      for (auto& e : edges) {
+        const int ja = rb[e.first], jbb = rb[e.second];
+        if (ja >= 0 && jbb >= 0) {
+          for (int jj = 0; jj < (1 << R); ++jj)
+            if (((jj >> ja) & 1) && ((jj >> jbb) & 1)) cr.sr ^= 1u << jj;
+        } else if (ja >= 0) {
+          cr.cmask[ja] ^= 1u << e.second;
+        } else {
+          cr.cmask[jbb] ^= 1u << e.first;
+        }
+      }
+      S.ops.push_back({OP_CZA, (int)S.cza.size(), cur, 0, 0, 0, 0, 0});
+      S.cza.push_back(cr);
+      S.n_cz++;
+    };
 
     while (true) {
       apply_free();
@@ -635,43 +672,11 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
         apply_free();
       }
       // items that still block the chosen runs touch register bits: per amplitude
-      std::vector<std::pair<int, int>> edges;
       std::vector<int> run_wires(want.begin(), want.begin() + n_run_wires);
+      std::vector<int> blocking;
       for (int q : run_wires)
-        for (int id : gap_items[q][runs_done[q]]) {
-          Item& it = items[id];
-          if (it.applied) continue;
-          it.applied = true;
-          S.n_diag_amp++;
-          if (it.kind == 1) {
-            edges.push_back({it.q0, it.q1});
-          } else {
-            int j = (int)(std::find(regq.begin(), regq.end(), q) - regq.begin());
-            const int eb = (int)S.pev.size();
-            S.pev.push_back(S.pev[it.ev]);
-            S.ops.push_back({OP_PHASEA, j, eb, 0, 0, 0, 0, 0});
-          }
-        }
-      if (!edges.empty()) {
-        CzaRec cr;
-        std::memset(&cr, 0, sizeof(cr));
-        std::vector<int> rb(n, -1);
-        for (int j = 0; j < R; ++j) rb[regq[j]] = j;
-        for (auto& e : edges) {
-          const int ja = rb[e.first], jbb = rb[e.second];
-          if (ja >= 0 && jbb >= 0) {
-            for (int jj = 0; jj < (1 << R); ++jj)
-              if (((jj >> ja) & 1) && ((jj >> jbb) & 1)) cr.sr ^= 1u << jj;
-          } else if (ja >= 0) {
-            cr.cmask[ja] ^= 1u << e.second;
-          } else {
-            cr.cmask[jbb] ^= 1u << e.first;
-          }
-        }
-        S.ops.push_back({OP_CZA, (int)S.cza.size(), cur, 0, 0, 0, 0, 0});
-        S.cza.push_back(cr);
-        S.n_cz++;
-      }
+        for (int id : gap_items[q][runs_done[q]]) blocking.push_back(id);
+      apply_amp(blocking);
       for (int j = 0; j < R; ++j) {
         const int q = regq[j];
         if (std::find(run_wires.begin(), run_wires.end(), q) == run_wires.end()) continue;
@@ -689,10 +694,22 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
     }
     pr.n_slots = slot;
     const bool last = (runs_left == 0);
-    if (last) {
+    if (last && !S.general_obs) {
       // only trailing diagonal gates remain; they commute with the Z-string
       // observables and change neither E nor the adjoint at the cuts
       S.ops.push_back({OP_EXPECT, cur, 0, 0, 0, 0, 0, 0});
+    } else if (last) {
+      // observables with X or Y parts: the trailing diagonal gates are applied
+      // too, so the stored final state is the circuit's output state, from
+      // which a separate kernel forms E and the adjoint seed
+      for (size_t id = 0; id < items.size(); ++id)
+        if (!items[id].applied && !items[id].released) {
+          items[id].released = true;
+          released_list.push_back((int)id);
+        }
+      apply_free();
+      apply_amp(released_list);
+      released_list.clear();
     }
 
     std::vector<int> out_map(n);
@@ -751,7 +768,10 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
     pr.fop_count = (int)S.ops.size() - fop_begin;
     S.passes.push_back(pr);
     ++pass_id;
-    if (last) break;
+    if (last) {
+      S.final_map.assign(out_map.begin(), out_map.end());
+      break;
+    }
     in_map = out_map;
     local = next_local;
   }
@@ -765,8 +785,8 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
     const Op st = f.back();
     const Op ld = f.front();
     b.push_back({OP_LOAD, st.a, 0, 1, 0, 0, 0, 0});
-    if (p == P - 1) b.push_back({OP_SEED, st.a, 0, 0, 0, 0, 0, 0});
-    else b.push_back({OP_LOAD, st.a, 1, 1, 0, 0, 0, 0});
+    if (p == P - 1 && !S.general_obs) b.push_back({OP_SEED, st.a, 0, 0, 0, 0, 0, 0});
+    else b.push_back({OP_LOAD, st.a, 1, 1, 0, 0, 0, 0});   // (general observables: the seed kernel's lambda)
     int i = (int)f.size() - 2;
     while (i >= 1) {
       const Op& o = f[i];

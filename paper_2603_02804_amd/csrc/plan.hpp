@@ -59,6 +59,11 @@ struct Schedule {
   std::vector<PhaseEv> pev;           // phase events referenced by DIAGT / PHASEA ops
   std::vector<CzaRec> cza;
   std::vector<int32_t> pass_run_begin, pass_runs;   // runs of each pass, slot order
+  // observables with X or Y parts: the last pass stores the full output state
+  // (trailing diagonal gates applied) in memory bit order final_map[qubit], and
+  // separate kernels form E and the adjoint seed from it
+  bool general_obs = false;
+  std::vector<int32_t> final_map;
   int max_slots = 0;
   // per-sample op counts over all forward passes
   int64_t n_perm = 0, n_u2 = 0, n_cz = 0;

@@ -63,6 +63,15 @@ struct PhaseEv {
   int32_t ref;    // event coefficient: >=0 shared row, <0 per-sample row -1-idx
 };
 
+// A Pauli-string observable i^ny X^xm Z^zm (Y where both masks are set; ny =
+// number of Y factors mod 4), masks in the bit order of the state it is applied
+// to: (P psi)_y = i^ny (-1)^{popcount((y ^ xm) & zm)} psi_{y ^ xm} (App. B.2).
+struct PauliRec {
+  uint32_t xm, zm;
+  int32_t ny;
+  int32_t pad;
+};
+
 // Per-amplitude CZ signs on a register layout: sign(jj) = bit jj of sr XOR
 // parity over register bits j set in jj of parity(A & cmask[j]), A = the
 // thread's logical base index (thread and tile bits).

@@ -612,34 +612,53 @@ struct CpuExec {
           }
         }
   }
-  void pg_expect(const float* psi, int nb, float* partE) {
+  // observables (any Pauli strings, masks in the stored state's bit order);
+  // strides count floats
+  void pauli_expect(const float* psi, int64_t stride, int nb, float* partE) {
+    const std::vector<PauliRec> ob = pauli_table(c);
     for (int s = 0; s < nb; ++s)
       for (int k = 0; k < c.C.K; ++k) {
+        const PauliRec& o = ob[k];
         double acc = 0;
-        for (int64_t i = 0; i < c.amps; ++i) {
-          double p = (double)psi[s * 2 * c.amps + 2 * i] * psi[s * 2 * c.amps + 2 * i] +
-                     (double)psi[s * 2 * c.amps + 2 * i + 1] * psi[s * 2 * c.amps + 2 * i + 1];
-          acc += (__builtin_popcountll((uint64_t)i & c.C.obs[k].z_mask) & 1) ? -p : p;
+        for (int64_t y = 0; y < c.amps; ++y) {
+          const int64_t yx = y ^ (int64_t)o.xm;
+          in_ws(psi + s * stride + 2 * y, 8, "expect address");
+          const double ar = psi[s * stride + 2 * y], ai = psi[s * stride + 2 * y + 1];
+          const double br = psi[s * stride + 2 * yx], bi = psi[s * stride + 2 * yx + 1];
+          double cr = ar * br + ai * bi, ci = ar * bi - ai * br;   // conj(a) b
+          for (int t = 0; t < o.ny; ++t) { const double tr = -ci; ci = cr; cr = tr; }
+          acc += (__builtin_popcountll((uint64_t)(yx & (int64_t)o.zm)) & 1) ? -cr : cr;
         }
-        for (int b = 0; b < c.pg_blocks; ++b) partE[((int64_t)s * c.pg_blocks + b) * c.C.K + k] = b == 0 ? (float)acc : 0.f;
+        for (int b = 0; b < c.pauli_blocks; ++b)
+          partE[((int64_t)s * c.pauli_blocks + b) * c.C.K + k] = b == 0 ? (float)acc : 0.f;
       }
   }
-  void pg_reduce_E(int nb, int sample0, const float* partE, float* E) {
+  void pauli_reduce_E(int nb, int sample0, const float* partE, float* E) {
     for (int s = 0; s < nb; ++s)
       for (int k = 0; k < c.C.K; ++k) {
         double acc = 0;
-        for (int b = 0; b < c.pg_blocks; ++b) acc += partE[((int64_t)s * c.pg_blocks + b) * c.C.K + k];
+        for (int b = 0; b < c.pauli_blocks; ++b) acc += partE[((int64_t)s * c.pauli_blocks + b) * c.C.K + k];
         E[(int64_t)(sample0 + s) * c.C.K + k] = (float)acc;
       }
   }
-  void pg_seed(const float* psi, float* lam, int nb, int sample0, const float* dE) {
+  void pauli_seed(const float* psi, int64_t ps, float* lam, int64_t ls, int nb, int sample0, const float* dE) {
+    const std::vector<PauliRec> ob = pauli_table(c);
     for (int s = 0; s < nb; ++s)
-      for (int64_t i = 0; i < c.amps; ++i) {
-        double cc = 0;
-        for (int k = 0; k < c.C.K; ++k)
-          cc += ((__builtin_popcountll((uint64_t)i & c.C.obs[k].z_mask) & 1) ? -1.0 : 1.0) * dE[(int64_t)(sample0 + s) * c.C.K + k];
-        lam[s * 2 * c.amps + 2 * i] = (float)(2 * cc * psi[s * 2 * c.amps + 2 * i]);
-        lam[s * 2 * c.amps + 2 * i + 1] = (float)(2 * cc * psi[s * 2 * c.amps + 2 * i + 1]);
+      for (int64_t y = 0; y < c.amps; ++y) {
+        double ar = 0, ai = 0;
+        for (int k = 0; k < c.C.K; ++k) {
+          const PauliRec& o = ob[k];
+          const int64_t yx = y ^ (int64_t)o.xm;
+          double g = dE[(int64_t)(sample0 + s) * c.C.K + k];
+          if (__builtin_popcountll((uint64_t)(yx & (int64_t)o.zm)) & 1) g = -g;
+          double tr = psi[s * ps + 2 * yx], ti = psi[s * ps + 2 * yx + 1];
+          for (int t = 0; t < o.ny; ++t) { const double u = -ti; ti = tr; tr = u; }
+          ar += g * tr;
+          ai += g * ti;
+        }
+        in_ws(lam + s * ls + 2 * y, 8, "seed address");
+        lam[s * ls + 2 * y] = (float)(2 * ar);
+        lam[s * ls + 2 * y + 1] = (float)(2 * ai);
       }
   }
   void pg_rot_bwd(float* psi, float* lam, int nb, int sample0, int r, int slot, const float*, const float*, float* partF) {
@@ -780,6 +799,7 @@ int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, i
       st = build_plan_core(C, samples[i], T, pcs.back().get(), &msg);
       if (st != QF_OK) { g_err = msg; return st; }
       const PlanCore& c = *pcs.back();
+      if (c.S.general_obs) { g_err = "mixed batches take Z-string observables only"; return QF_ERR_UNSUPPORTED; }
       cores.push_back(&c);
       PlanPtrs pp;   // host copies of the tables: only their addresses enter the jobs
       pp.ops = c.S.ops.data(); pp.layouts = c.S.layouts.data(); pp.czg = c.S.czg.data();

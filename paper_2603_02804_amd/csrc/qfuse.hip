@@ -18,7 +18,9 @@
 //                       dL/dtheta_g = Re<lambda_g|du_g|psi_{g-1}> = 1/2 Im<lambda|G_g|psi>
 //                       with G_g = K_g P_g K_g^dagger, K_g = later gates of the run.
 //   k_reduce_grads      sums over the batch (theta) and over shared angles, fixed order.
-//   k_reduce_E          expectation partial sums -> E[b][k] (App. B.2, Z strings).
+//   k_reduce_E          expectation partial sums -> E[b][k] (App. B.2).
+//   k_pauli_expect/seed expectations and adjoint seed of general Pauli strings
+//                       from a stored state (App. B.2).
 //   k_pg_*              one-kernel-per-gate baseline.
 // The kernel bodies live in device.hpp, shared with the merged mixed-batch
 // kernels of batch.hip.
@@ -171,39 +173,73 @@ __device__ inline void block_reduce(Real (&v)[NV], Real* out, int count) {
   }
 }
 
+// i^ny * z
+template <class V>
+__device__ __forceinline__ V mul_i_pow(V z, int ny) {
+  V r = z;
+  if (ny & 1) { r.x = -z.y; r.y = z.x; }
+  if (ny & 2) { r.x = -r.x; r.y = -r.y; }
+  return r;
+}
+
+// Pauli-string expectations (App. B.2): per block, partial sums over its
+// amplitudes y of Re conj(psi_y) (P_k psi)_y with (P psi)_y =
+// i^ny (-1)^{popcount((y ^ xm) & zm)} psi_{y ^ xm}.  The masks are in the bit
+// order of the stored state.  Blocks of one sample: `blocks`.
 template <class Real>
-__global__ __launch_bounds__(kPgThreads) void k_pg_expect(const typename Cplx<Real>::T* psi, long long amps, int K,
-                                                          const uint32_t* zmask, Real* partE, int blocks) {
+__global__ __launch_bounds__(kPgThreads) void k_pauli_expect(const typename Cplx<Real>::T* psi, long long stride,
+                                                             long long amps, int K, const PauliRec* obs, Real* partE,
+                                                             int blocks) {
   using V = typename Cplx<Real>::T;
   const int s = blockIdx.x / blocks, blk = blockIdx.x - s * blocks;
-  const V* v = psi + (long long)s * amps;
+  const V* v = psi + (long long)s * stride;
   for (int k0 = 0; k0 < K; k0 += 8) {
     Real acc[8];
     for (int k = 0; k < 8; ++k) acc[k] = 0;
-    for (int k2 = 0; k2 < 2 * kPgPairsPerThread; ++k2) {
-      const long long i = ((long long)blk * 2 * kPgPairsPerThread + k2) * kPgThreads + threadIdx.x;
-      if (i >= amps) break;
-      const Real p = v[i].x * v[i].x + v[i].y * v[i].y;
-      for (int k = 0; k < 8; ++k)
-        if (k0 + k < K) acc[k] += (__popcll((unsigned long long)i & zmask[k0 + k]) & 1) ? -p : p;
+    for (int k2 = 0; k2 < kPauliAmpsPerThread; ++k2) {
+      const long long y = ((long long)blk * kPauliAmpsPerThread + k2) * kPgThreads + threadIdx.x;
+      if (y >= amps) break;
+      const V a = v[y];
+      for (int k = 0; k < 8; ++k) {
+        if (k0 + k >= K) break;
+        const PauliRec o = obs[k0 + k];
+        const long long yx = y ^ (long long)o.xm;
+        const V b = v[yx];
+        // conj(a) * b, times i^ny, real part, times the sign
+        V c;
+        c.x = a.x * b.x + a.y * b.y;
+        c.y = a.x * b.y - a.y * b.x;
+        const Real re = mul_i_pow(c, o.ny).x;
+        acc[k] += (__popcll((unsigned long long)(yx & (long long)o.zm)) & 1) ? -re : re;
+      }
     }
     block_reduce<8>(acc, partE + ((long long)s * blocks + blk) * K + k0, K - k0);
     __syncthreads();
   }
 }
 
+// Adjoint seed lambda = 2 sum_k g_k P_k psi (eq. bwd_exp_val with the chain
+// rule), one thread per amplitude.
 template <class Real>
-__global__ void k_pg_seed(const typename Cplx<Real>::T* psi, typename Cplx<Real>::T* lam, long long amps, int nb,
-                          int sample0, int K, const uint32_t* zmask, const Real* dE) {
+__global__ void k_pauli_seed(const typename Cplx<Real>::T* psi, long long psi_stride, typename Cplx<Real>::T* lam,
+                             long long lam_stride, long long amps, int nb, int sample0, int K, const PauliRec* obs,
+                             const Real* dE) {
+  using V = typename Cplx<Real>::T;
   const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= amps * nb) return;
-  const long long s = idx / amps, i = idx - s * amps;
-  Real c = 0;
+  const long long s = idx / amps, y = idx - s * amps;
+  const V* v = psi + s * psi_stride;
+  V acc = Cplx<Real>::make(0, 0);
   for (int k = 0; k < K; ++k) {
+    const PauliRec o = obs[k];
+    const long long yx = y ^ (long long)o.xm;
     const Real g = dE[(sample0 + s) * K + k];
-    c += (__popcll((unsigned long long)i & zmask[k]) & 1) ? -g : g;
+    const Real w = (__popcll((unsigned long long)(yx & (long long)o.zm)) & 1) ? -g : g;
+    const V t = mul_i_pow(v[yx], o.ny);
+    acc.x += w * t.x;
+    acc.y += w * t.y;
   }
-  lam[idx] = Cplx<Real>::make(2 * c * psi[idx].x, 2 * c * psi[idx].y);
+  lam[s * lam_stride + y] = Cplx<Real>::make(2 * acc.x, 2 * acc.y);
 }
 
 // Backward of one gate: the functionals Im<lambda|P|psi> (P = X, Y, Z) at the
@@ -416,29 +452,33 @@ struct GpuExec {
     pe(2);
     check("k_pg_cz");
   }
+  // observables (any Pauli strings) of stored states; strides count reals
   template <class Real>
-  void pg_expect(const Real* psi, int nb, Real* partE) {
+  void pauli_expect(const Real* psi, int64_t stride, int nb, Real* partE) {
     pb();
-    hipLaunchKernelGGL(k_pg_expect<Real>, dim3(nb * c.pg_blocks), dim3(kPgThreads), 0, st, (const V<Real>*)psi,
-                       (long long)c.amps, c.C.K, d.p.zmask, partE, c.pg_blocks);
+    hipLaunchKernelGGL(k_pauli_expect<Real>, dim3(nb * c.pauli_blocks), dim3(kPgThreads), 0, st,
+                       (const V<Real>*)psi, (long long)(stride / 2), (long long)c.amps, c.C.K, d.p.pauli, partE,
+                       c.pauli_blocks);
     pe(2);
-    check("k_pg_expect");
+    check("k_pauli_expect");
   }
   template <class Real>
-  void pg_reduce_E(int nb, int sample0, const Real* partE, Real* E) {
-    const ReduceEArgsT<Real> a = make_reduce_E_args<Real>(c, nb, sample0, c.pg_blocks, partE, E);
+  void pauli_reduce_E(int nb, int sample0, const Real* partE, Real* E) {
+    const ReduceEArgsT<Real> a = make_reduce_E_args<Real>(c, nb, sample0, c.pauli_blocks, partE, E);
     pb();
     hipLaunchKernelGGL(k_reduce_E<Real>, dim3(blocks_for((long long)nb * c.C.K)), dim3(kSmallThreads), 0, st, a);
     pe(2);
     check("k_reduce_E");
   }
   template <class Real>
-  void pg_seed(const Real* psi, Real* lam, int nb, int sample0, const Real* dE) {
+  void pauli_seed(const Real* psi, int64_t psi_stride, Real* lam, int64_t lam_stride, int nb, int sample0,
+                  const Real* dE) {
     pb();
-    hipLaunchKernelGGL(k_pg_seed<Real>, dim3(blocks_for(c.amps * nb)), dim3(256), 0, st, (const V<Real>*)psi,
-                       (V<Real>*)lam, (long long)c.amps, nb, sample0, c.C.K, d.p.zmask, dE);
+    hipLaunchKernelGGL(k_pauli_seed<Real>, dim3(blocks_for(c.amps * nb)), dim3(256), 0, st, (const V<Real>*)psi,
+                       (long long)(psi_stride / 2), (V<Real>*)lam, (long long)(lam_stride / 2), (long long)c.amps, nb,
+                       sample0, c.C.K, d.p.pauli, dE);
     pe(2);
-    check("k_pg_seed");
+    check("k_pauli_seed");
   }
   template <class Real>
   void pg_rot_bwd(Real* psi, Real* lam, int nb, int sample0, int r, int slot, const Real* cs, const Real* cpp,

@@ -46,20 +46,22 @@ def lib():
     return _lib
 
 
-def _desc(n, gates, n_params, n_inputs, zmask):
+def _desc(n, gates, n_params, n_inputs, zmask, xmask=None):
     gates = np.ascontiguousarray(gates, dtype=np.int32).reshape(-1, 5)
     obs = np.zeros((len(zmask), 2), dtype=np.uint64)
     obs[:, 1] = np.asarray(zmask, dtype=np.uint64)
+    if xmask is not None:
+        obs[:, 0] = np.asarray(xmask, dtype=np.uint64)
     d = Desc(n, n_params, n_inputs, gates.ctypes.data, len(gates), obs.ctypes.data, len(zmask))
     return d, (gates, obs)
 
 
-def run(n, gates, theta, x, zmask, dE=None, **tuning):
+def run(n, gates, theta, x, zmask, dE=None, xmask=None, **tuning):
     theta = np.ascontiguousarray(theta, dtype=np.float32)
     x = np.ascontiguousarray(x, dtype=np.float32)
     B = x.shape[0]
     K = len(zmask)
-    d, keep = _desc(n, gates, len(theta), x.shape[1], zmask)
+    d, keep = _desc(n, gates, len(theta), x.shape[1], zmask, xmask)
     t = make_tuning(**tuning)
     E = np.zeros((B, K), dtype=np.float32)
     dth = np.zeros(len(theta), dtype=np.float32)

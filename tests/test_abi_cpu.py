@@ -85,7 +85,9 @@ RX, RY, RZ, CZ = 0, 1, 2, 3
     (2, [[RY, 0, -1, 1, -1]], 1, 0, (1,), None, INVALID),               # theta_idx >= n_params
     (2, [[RY, 0, -1, -1, 3]], 1, 3, (1,), None, INVALID),               # input_idx >= n_inputs
     (2, [[RY, 0, -1, 0, -1]], 1, 0, (4,), None, INVALID),               # observable beyond the register
-    (2, [[RY, 0, -1, 0, -1]], 1, 0, (1,), (1,), UNSUPPORTED),           # X part in an observable
+    (2, [[RY, 0, -1, 0, -1]], 1, 0, (1,), (1,), QF_OK),                 # Y on qubit 0
+    (2, [[RY, 0, -1, 0, -1]], 1, 0, (0,), (3,), QF_OK),                 # XX
+    (2, [[RY, 0, -1, 0, -1]], 1, 0, (0,), (4,), INVALID),               # X beyond the register
 ])
 def test_circuit_validation(lib, n, gates, P, F, z, x, want):
     desc, _keep = _desc(n, gates, P, F, z, x)
@@ -118,6 +120,8 @@ def test_null_arguments(lib):
     (1, qfuse.make_tuning(tile_qubits=14)),               # tile beyond 2^13 amplitudes
     (1, qfuse.make_tuning(reg_qubits=6)),                 # more register qubits than supported
     (1, qfuse.make_tuning(ckpt_interval=-1)),             # negative value
+    (1, qfuse.make_tuning(mem_save=2)),                   # mem_save is a flag
+    (1, qfuse.make_tuning(mode=1, mem_save=1)),           # memory-saving mode is for fused plans
 ])
 def test_plan_validation_before_any_device_call(lib, batch, tuning):
     desc, _keep = _desc(2, [[RY, 0, -1, 0, -1], [CZ, 0, 1, -1, -1]])
