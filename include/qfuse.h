@@ -66,8 +66,12 @@ typedef enum { QF_RX = 0, QF_RY = 1, QF_RZ = 2, QF_CZ = 3 } qf_gate_kind;
  */
 typedef struct { int32_t kind, q0, q1, theta_idx, input_idx; } qf_gate;
 
-/* Pauli-string observable: X on x_mask bits, Z on z_mask bits (Y on both).
-   The hot path supports Z strings only (x_mask == 0); others: QF_ERR_UNSUPPORTED. */
+/* Pauli-string observable: X on x_mask bits, Z on z_mask bits (Y on both),
+   i.e. i^{#Y} X^{x_mask} Z^{z_mask} (App. B.2).  Z strings (x_mask == 0) are
+   evaluated inside the last fused pass.  A circuit with any X or Y factor has its
+   trailing diagonal gates applied too (they do not commute with X or Y), and E
+   and the adjoint seed are formed from the stored output state by separate
+   kernels.  Mixed batches (qf_batch_create) take Z strings only. */
 typedef struct { uint64_t x_mask, z_mask; } qf_pauli;
 
 typedef struct {
@@ -169,6 +173,22 @@ qf_status qf_backward(qf_plan* plan, const float* theta, const float* x, const f
                       float* dtheta, float* dx, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * The same calls from given initial states instead of |0...0> (the paper's own
+ * experiments start from random states, Sec. 4).  psi0: device complex64
+ * [batch][2^n_qubits], interleaved (re, im), amplitude index x = sum_i x_i 2^i;
+ * not normalised by the library.  The first fused pass reads it in place; the
+ * backward reads it again to recompute the first checkpoint segment, so it
+ * must be the same buffer, unchanged, in the matching qf_backward_psi0.  No
+ * gradient is formed with respect to psi0.  psi0 == NULL is |0...0>, i.e.
+ * qf_forward / qf_backward.
+ */
+qf_status qf_forward_psi0(qf_plan* plan, const float* theta, const float* x, const float* psi0,
+                          float* E, void* ws, size_t ws_bytes, void* stream);
+qf_status qf_backward_psi0(qf_plan* plan, const float* theta, const float* x, const float* psi0,
+                           const float* dE, float* dtheta, float* dx, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/*
  * Complex128 validation path (plans created with mode QF_MODE_C128).  The same
  * quantities as qf_forward / qf_backward (Sec. 2.1 expectations; Sec. 2.2
  * adjoint gradients, eq. grad_theta and eq. update_adjoint_state) computed in
@@ -181,9 +201,11 @@ qf_status qf_backward(qf_plan* plan, const float* theta, const float* x, const f
  * QF_ERR_INVALID_ARG, and these calls reject any other plan the same way.
  * Workspace: qf_workspace_size of the plan (final states of the batch, two
  * working states per micro-batch sample, partial sums, coefficient tables).
+ * psi0: device complex128 [batch][2^n_qubits] initial states, or NULL for
+ * |0...0> (the backward needs no psi0: it starts from the stored final states).
  */
-qf_status qf_forward_c128(qf_plan* plan, const double* theta, const double* x, double* E,
-                          void* ws, size_t ws_bytes, void* stream);
+qf_status qf_forward_c128(qf_plan* plan, const double* theta, const double* x, const double* psi0,
+                          double* E, void* ws, size_t ws_bytes, void* stream);
 qf_status qf_backward_c128(qf_plan* plan, const double* theta, const double* x, const double* dE,
                            double* dtheta, double* dx, void* ws, size_t ws_bytes, void* stream);
 
@@ -236,8 +258,9 @@ typedef struct {
 
 /*
  * circuits[i] is simulated for samples[i] >= 1 samples.  tuning (may be NULL)
- * applies to every circuit's plan; mode must be 0 (fused).  The plans and merged
- * tables live on the current HIP device.
+ * applies to every circuit's plan; mode must be 0 (fused); mem_save may be set.
+ * Circuits whose observables have X or Y factors: QF_ERR_UNSUPPORTED.  The
+ * plans and merged tables live on the current HIP device.
  */
 qf_status qf_batch_create(const qf_circuit* const* circuits, const int32_t* samples, int32_t n_circuits,
                           const qf_tuning* tuning, qf_batch** out);

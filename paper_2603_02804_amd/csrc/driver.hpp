@@ -39,6 +39,7 @@ struct PassLaunch {
   float* partE = nullptr;   // forward expectation partial sums
   const float* dE = nullptr;
   int do_expect = 0;
+  bool load_input = false;  // pass 0 reads a caller's initial state from src0
 };
 
 struct PlanCore {
@@ -236,7 +237,8 @@ inline T* at(char* ws, size_t off) {
 // O(2^n) amplitudes).
 // Real is float on the baseline and double on the complex128 validation path.
 template <class Real, class Exec>
-qf_status run_forward_pg(const PlanCore& c, Exec& ex, const Real* theta, const Real* x, Real* E, char* ws) {
+qf_status run_forward_pg(const PlanCore& c, Exec& ex, const Real* theta, const Real* x, Real* E, char* ws,
+                         const Real* psi0 = nullptr) {
   const int64_t SA = 2 * c.amps;
   const Real* csh = at<Real>(ws, c.off_coef_sh);
   const Real* cps = at<Real>(ws, c.off_coef_ps);
@@ -244,7 +246,8 @@ qf_status run_forward_pg(const PlanCore& c, Exec& ex, const Real* theta, const R
   for (int mb0 = 0; mb0 < c.B; mb0 += c.mb) {
     const int nb = std::min(c.mb, c.B - mb0);
     Real* psi = at<Real>(ws, c.off_ckpt) + int64_t(mb0) * SA;
-    ex.pg_init(psi, nb);
+    if (psi0) ex.pg_copy(psi, psi0 + int64_t(mb0) * SA, nb);
+    else ex.pg_init(psi, nb);
     int r = 0;
     for (const qf_gate& g : c.C.gates) {
       if (g.kind == QF_CZ) ex.pg_cz(psi, (Real*)nullptr, nb, g.q0, g.q1);
@@ -296,7 +299,8 @@ qf_status run_backward_pg(const PlanCore& c, Exec& ex, const Real* theta, const 
 // per-sample stride (floats).
 template <class Exec>
 std::pair<const float*, int64_t> forward_passes(const PlanCore& c, Exec& ex, char* ws, int mb0, int nb,
-                                                bool keep_ckpt, float* ckpt_base, bool do_expect) {
+                                                bool keep_ckpt, float* ckpt_base, bool do_expect,
+                                                const float* psi0) {
   const int64_t SA = 2 * c.amps;   // floats per state
   float* work = at<float>(ws, c.off_work);
   float* partE = at<float>(ws, c.off_partE);
@@ -311,6 +315,11 @@ std::pair<const float*, int64_t> forward_passes(const PlanCore& c, Exec& ex, cha
     L.sample0 = mb0;
     L.src0 = src;
     L.src0_stride = src_stride;
+    if (p == 0 && psi0) {   // a given initial state, logical order
+      L.src0 = psi0 + int64_t(mb0) * SA;
+      L.src0_stride = SA;
+      L.load_input = true;
+    }
     if (keep_ckpt && seg_end) {
       L.dst = ckpt_base + s * SA;
       L.dst_stride = SA * c.n_seg;
@@ -328,13 +337,14 @@ std::pair<const float*, int64_t> forward_passes(const PlanCore& c, Exec& ex, cha
 }
 
 template <class Exec>
-qf_status run_forward_fused(const PlanCore& c, Exec& ex, const float* theta, const float* x, float* E, char* ws) {
+qf_status run_forward_fused(const PlanCore& c, Exec& ex, const float* theta, const float* x, float* E, char* ws,
+                            const float* psi0 = nullptr) {
   const int64_t SA = 2 * c.amps;
   ex.coef(theta, x, ws);
   for (int mb0 = 0; mb0 < c.B; mb0 += c.mb) {
     const int nb = std::min(c.mb, c.B - mb0);
     float* ck = at<float>(ws, c.off_ckpt) + (c.store ? int64_t(mb0) * c.n_seg * SA : 0);
-    const auto fin = forward_passes(c, ex, ws, mb0, nb, c.store != 0, ck, true);
+    const auto fin = forward_passes(c, ex, ws, mb0, nb, c.store != 0, ck, true, psi0);
     if (c.S.general_obs) {
       // X / Y observables: from the stored output state, in its bit order
       ex.pauli_expect(fin.first, fin.second, nb, at<float>(ws, c.off_partE));
@@ -348,7 +358,7 @@ qf_status run_forward_fused(const PlanCore& c, Exec& ex, const float* theta, con
 
 template <class Exec>
 qf_status run_backward_fused(const PlanCore& c, Exec& ex, const float* theta, const float* x, const float* dE,
-                             float* dtheta, float* dx, char* ws) {
+                             float* dtheta, float* dx, char* ws, const float* psi0 = nullptr) {
   const int64_t SA = 2 * c.amps;
   const int64_t SS = c.memsave ? c.amps : SA;   // words per stored pass output
   const bool bf = c.memsave != 0;
@@ -360,7 +370,7 @@ qf_status run_backward_fused(const PlanCore& c, Exec& ex, const float* theta, co
   for (int mb0 = 0; mb0 < c.B; mb0 += c.mb) {
     const int nb = std::min(c.mb, c.B - mb0);
     float* ck = at<float>(ws, c.off_ckpt) + (c.store ? int64_t(mb0) * c.n_seg * SA : 0);
-    if (!c.store) forward_passes(c, ex, ws, mb0, nb, true, ck, false);
+    if (!c.store) forward_passes(c, ex, ws, mb0, nb, true, ck, false, psi0);
     const int64_t ck_stride = SA * c.n_seg;
     int li = 0;
     for (int s = c.n_seg - 1; s >= 0; --s) {
@@ -373,6 +383,7 @@ qf_status run_backward_fused(const PlanCore& c, Exec& ex, const float* theta, co
         L.sample0 = mb0;
         if (p == a) {
           if (s > 0) { L.src0 = ck + (s - 1) * SA; L.src0_stride = ck_stride; }
+          else if (psi0) { L.src0 = psi0 + int64_t(mb0) * SA; L.src0_stride = SA; L.load_input = true; }
         } else if (bf) {
           // the recompute continues from the float32 output of the previous pass
           L.src0 = work + ((p - 1) & 1) * SA * nb;
@@ -418,17 +429,20 @@ qf_status run_backward_fused(const PlanCore& c, Exec& ex, const float* theta, co
   return ex.status();
 }
 
+// psi0: the initial states of the batch (complex64, logical order), or null
+// for |0...0>; the backward needs the same psi0 as the forward.
 template <class Exec>
-qf_status run_forward(const PlanCore& c, Exec& ex, const float* theta, const float* x, float* E, char* ws) {
-  if (c.per_gate) return run_forward_pg(c, ex, theta, x, E, ws);
-  return run_forward_fused(c, ex, theta, x, E, ws);
+qf_status run_forward(const PlanCore& c, Exec& ex, const float* theta, const float* x, float* E, char* ws,
+                      const float* psi0 = nullptr) {
+  if (c.per_gate) return run_forward_pg(c, ex, theta, x, E, ws, psi0);
+  return run_forward_fused(c, ex, theta, x, E, ws, psi0);
 }
 
 template <class Exec>
 qf_status run_backward(const PlanCore& c, Exec& ex, const float* theta, const float* x, const float* dE,
-                       float* dtheta, float* dx, char* ws) {
+                       float* dtheta, float* dx, char* ws, const float* psi0 = nullptr) {
   if (c.per_gate) return run_backward_pg(c, ex, theta, x, dE, dtheta, dx, ws);
-  return run_backward_fused(c, ex, theta, x, dE, dtheta, dx, ws);
+  return run_backward_fused(c, ex, theta, x, dE, dtheta, dx, ws, psi0);
 }
 
 }  // namespace qf

@@ -105,7 +105,7 @@ inline KArgs make_pass_args(const PlanCore& c, const PlanPtrs& d, const CoefPtrs
   const Schedule& S = c.S;
   const PassRec& pr = S.passes[L.pass];
   KArgs A;
-  A.ops = d.ops + (L.bwd ? pr.bop_begin : pr.fop_begin);
+  A.ops = d.ops + (L.bwd ? pr.bop_begin : (L.load_input ? pr.fload_begin : pr.fop_begin));
   A.n_ops = L.bwd ? pr.bop_count : pr.fop_count;
   A.layouts = d.layouts;
   A.czg = d.czg;

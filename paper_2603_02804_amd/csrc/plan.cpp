@@ -819,6 +819,16 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
   }
   group_register_runs(&S);
   fuse_epochs(&S);
+  // pass 0 also as a program that loads a given initial state: its input bit
+  // order is the logical one, so the state is read as the caller holds it
+  for (PassRec& pr : S.passes) pr.fload_begin = -1;
+  if (!S.passes.empty() && S.ops[S.passes[0].fop_begin].kind == OP_INIT0) {
+    PassRec& p0 = S.passes[0];
+    std::vector<Op> f(S.ops.begin() + p0.fop_begin, S.ops.begin() + p0.fop_begin + p0.fop_count);
+    f[0] = {OP_LOAD, f[0].a, 0, 0, 0, 0, 0, 0};
+    p0.fload_begin = (int)S.ops.size();
+    S.ops.insert(S.ops.end(), f.begin(), f.end());
+  }
   if (runs_left != 0) {
     if (msg) *msg = "scheduler left runs unapplied";
     return false;

@@ -155,7 +155,9 @@ struct PassRec {
   int32_t bop_begin, bop_count;   // backward program
   int32_t n_nonlocal;
   int32_t n_slots;                // fused runs whose functionals the backward writes
-  int32_t pad[2];
+  int32_t fload_begin;            // pass 0: forward program that loads a caller's initial
+                                  // state (logical order) instead of generating |0...0>; -1
+  int32_t pad;
   uint8_t nl_log[32], nl_in[32], nl_out[32];
 };
 

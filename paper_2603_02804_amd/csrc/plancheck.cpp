@@ -91,8 +91,11 @@ struct CpuExec {
   const PlanCore& c;
   const char* ws_lo = nullptr;   // workspace range every state / partial access must stay in
   const char* ws_hi = nullptr;
+  const char* in_lo = nullptr;   // caller's initial states: the other range reads may use
+  const char* in_hi = nullptr;
   void in_ws(const void* p, size_t bytes, const char* what) const {
     const char* q = (const char*)p;
+    if (in_lo && q >= in_lo && q + bytes <= in_hi) return;
     if (ws_lo && (q < ws_lo || q + bytes > ws_hi)) oob(what);
   }
   const float* theta = nullptr;
@@ -206,7 +209,7 @@ struct CpuExec {
     const PassRec& pr = S.passes[L.pass];
     const int R = S.R, NA = 1 << R, tb = S.thread_bits, active = S.active;
     const int tiles = c.tiles, waves = c.waves, K = c.C.K;
-    const int b0 = L.bwd ? pr.bop_begin : pr.fop_begin;
+    const int b0 = L.bwd ? pr.bop_begin : (L.load_input ? pr.fload_begin : pr.fop_begin);
     const int nops = L.bwd ? pr.bop_count : pr.fop_count;
     const int64_t k_amps = int64_t(1) << S.k;
     std::vector<CF> a(size_t(active) * NA), l(size_t(active) * NA), lds(k_amps);
@@ -712,8 +715,8 @@ extern "C" {
 
 // Runs forward and backward for a circuit on host arrays through the planner's
 // programs.  Returns 0 on success, otherwise a qf_status with qfc_last_error().
-int qfc_run(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tuning, const float* theta,
-            const float* x, const float* dE, float* E, float* dtheta, float* dx) {
+int qfc_run_psi0(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tuning, const float* theta,
+                 const float* x, const float* psi0, const float* dE, float* E, float* dtheta, float* dx) {
   try {
     std::string msg;
     qf_status st = validate_circuit(desc, &msg);
@@ -736,13 +739,22 @@ int qfc_run(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tuning,
     CpuExec ex(pc);
     ex.ws_lo = base;
     ex.ws_hi = base + pc.ws_bytes;
-    run_forward(pc, ex, theta, x, E, base);
-    if (dE) run_backward(pc, ex, theta, x, dE, dtheta, dx, base);
+    if (psi0) {
+      ex.in_lo = (const char*)psi0;
+      ex.in_hi = ex.in_lo + pc.state_bytes * batch;
+    }
+    run_forward(pc, ex, theta, x, E, base, psi0);
+    if (dE) run_backward(pc, ex, theta, x, dE, dtheta, dx, base, psi0);
     return 0;
   } catch (const std::exception& e) {
     g_err = e.what();
     return QF_ERR_INTERNAL;
   }
+}
+
+int qfc_run(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tuning, const float* theta,
+            const float* x, const float* dE, float* E, float* dtheta, float* dx) {
+  return qfc_run_psi0(desc, batch, tuning, theta, x, nullptr, dE, E, dtheta, dx);
 }
 
 // Schedule statistics: passes, segments, ops, layout count.

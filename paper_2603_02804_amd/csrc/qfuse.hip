@@ -722,8 +722,8 @@ static qf_status check_call(qf_plan* p, void* ws, size_t ws_bytes) {
   return QF_OK;
 }
 
-qf_status qf_forward(qf_plan* p, const float* theta, const float* x, float* E, void* ws, size_t ws_bytes,
-                     void* stream) {
+qf_status qf_forward_psi0(qf_plan* p, const float* theta, const float* x, const float* psi0, float* E, void* ws,
+                          size_t ws_bytes, void* stream) {
   qf_status st = check_call(p, ws, ws_bytes);
   if (st != QF_OK) return st;
   const PlanCore& c = p->core;
@@ -731,13 +731,18 @@ qf_status qf_forward(qf_plan* p, const float* theta, const float* x, float* E, v
   if (!E || (c.C.P > 0 && !theta) || (c.C.F > 0 && !x)) return fail(QF_ERR_INVALID_ARG, "NULL buffer");
   GpuExec ex(c, p->dev, (hipStream_t)stream);
   ex.prof = &p->prof;
-  st = run_forward(c, ex, theta, x, E, (char*)ws);
+  st = run_forward(c, ex, theta, x, E, (char*)ws, psi0);
   if (st != QF_OK) return fail(st, ex.msg);
   return QF_OK;
 }
 
-qf_status qf_backward(qf_plan* p, const float* theta, const float* x, const float* dE, float* dtheta, float* dx,
-                      void* ws, size_t ws_bytes, void* stream) {
+qf_status qf_forward(qf_plan* p, const float* theta, const float* x, float* E, void* ws, size_t ws_bytes,
+                     void* stream) {
+  return qf_forward_psi0(p, theta, x, nullptr, E, ws, ws_bytes, stream);
+}
+
+qf_status qf_backward_psi0(qf_plan* p, const float* theta, const float* x, const float* psi0, const float* dE,
+                           float* dtheta, float* dx, void* ws, size_t ws_bytes, void* stream) {
   qf_status st = check_call(p, ws, ws_bytes);
   if (st != QF_OK) return st;
   const PlanCore& c = p->core;
@@ -749,13 +754,18 @@ qf_status qf_backward(qf_plan* p, const float* theta, const float* x, const floa
   ex.theta = theta;
   ex.x = x;
   ex.cp = coef_ptrs(c, (char*)ws);
-  st = run_backward(c, ex, theta, x, dE, dtheta, dx, (char*)ws);
+  st = run_backward(c, ex, theta, x, dE, dtheta, dx, (char*)ws, psi0);
   if (st != QF_OK) return fail(st, ex.msg);
   return QF_OK;
 }
 
-qf_status qf_forward_c128(qf_plan* p, const double* theta, const double* x, double* E, void* ws, size_t ws_bytes,
-                          void* stream) {
+qf_status qf_backward(qf_plan* p, const float* theta, const float* x, const float* dE, float* dtheta, float* dx,
+                      void* ws, size_t ws_bytes, void* stream) {
+  return qf_backward_psi0(p, theta, x, nullptr, dE, dtheta, dx, ws, ws_bytes, stream);
+}
+
+qf_status qf_forward_c128(qf_plan* p, const double* theta, const double* x, const double* psi0, double* E,
+                          void* ws, size_t ws_bytes, void* stream) {
   qf_status st = check_call(p, ws, ws_bytes);
   if (st != QF_OK) return st;
   const PlanCore& c = p->core;
@@ -763,7 +773,7 @@ qf_status qf_forward_c128(qf_plan* p, const double* theta, const double* x, doub
   if (!E || (c.C.P > 0 && !theta) || (c.C.F > 0 && !x)) return fail(QF_ERR_INVALID_ARG, "NULL buffer");
   GpuExec ex(c, p->dev, (hipStream_t)stream);
   ex.prof = &p->prof;
-  st = run_forward_pg<double>(c, ex, theta, x, E, (char*)ws);
+  st = run_forward_pg<double>(c, ex, theta, x, E, (char*)ws, psi0);
   if (st != QF_OK) return fail(st, ex.msg);
   return QF_OK;
 }

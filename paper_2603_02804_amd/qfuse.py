@@ -95,7 +95,9 @@ def library() -> ctypes.CDLL:
             "qf_workspace_size": [P, P],
             "qf_forward": [P, P, P, P, P, SZ, P],
             "qf_backward": [P, P, P, P, P, P, P, SZ, P],
-            "qf_forward_c128": [P, P, P, P, P, SZ, P],
+            "qf_forward_psi0": [P, P, P, P, P, P, SZ, P],
+            "qf_backward_psi0": [P, P, P, P, P, P, P, P, SZ, P],
+            "qf_forward_c128": [P, P, P, P, P, P, SZ, P],
             "qf_backward_c128": [P, P, P, P, P, P, P, SZ, P],
             "qf_profile_enable": [P, ctypes.c_int], "qf_profile_read": [P, P],
             "qf_batch_create": [P, P, I32, P, P], "qf_batch_destroy": [P], "qf_batch_get_info": [P, P],
@@ -167,9 +169,21 @@ def qf_backward(plan, theta: torch.Tensor, x: Optional[torch.Tensor], dE: torch.
                                  ws_bytes, stream))
 
 
-def qf_forward_c128(plan, theta: torch.Tensor, x: Optional[torch.Tensor], E: torch.Tensor, ws: torch.Tensor,
-                    ws_bytes: int, stream) -> None:
-    _check(library().qf_forward_c128(plan, _ptr(theta), _ptr(x), _ptr(E), _ptr(ws), ws_bytes, stream))
+def qf_forward_psi0(plan, theta: torch.Tensor, x: Optional[torch.Tensor], psi0: Optional[torch.Tensor],
+                    E: torch.Tensor, ws: torch.Tensor, ws_bytes: int, stream) -> None:
+    _check(library().qf_forward_psi0(plan, _ptr(theta), _ptr(x), _ptr(psi0), _ptr(E), _ptr(ws), ws_bytes, stream))
+
+
+def qf_backward_psi0(plan, theta: torch.Tensor, x: Optional[torch.Tensor], psi0: Optional[torch.Tensor],
+                     dE: torch.Tensor, dtheta: torch.Tensor, dx: Optional[torch.Tensor], ws: torch.Tensor,
+                     ws_bytes: int, stream) -> None:
+    _check(library().qf_backward_psi0(plan, _ptr(theta), _ptr(x), _ptr(psi0), _ptr(dE), _ptr(dtheta), _ptr(dx),
+                                      _ptr(ws), ws_bytes, stream))
+
+
+def qf_forward_c128(plan, theta: torch.Tensor, x: Optional[torch.Tensor], psi0: Optional[torch.Tensor],
+                    E: torch.Tensor, ws: torch.Tensor, ws_bytes: int, stream) -> None:
+    _check(library().qf_forward_c128(plan, _ptr(theta), _ptr(x), _ptr(psi0), _ptr(E), _ptr(ws), ws_bytes, stream))
 
 
 def qf_backward_c128(plan, theta: torch.Tensor, x: Optional[torch.Tensor], dE: torch.Tensor, dtheta: torch.Tensor,
@@ -248,26 +262,44 @@ class Plan:
             if x is None or x.dtype != dt or not x.is_cuda or tuple(x.shape) != (self.batch, c.n_inputs):
                 raise ValueError(f"x must be a {dt} CUDA tensor of shape [batch, n_inputs]")
 
+    def _check_psi0(self, psi0):
+        if psi0 is None:
+            return None
+        want = torch.complex128 if self.c128 else torch.complex64
+        if psi0.dtype != want or not psi0.is_cuda or tuple(psi0.shape) != (self.batch, 1 << self.circuit.n_qubits):
+            raise ValueError(f"psi0 must be a {want} CUDA tensor of shape [batch, 2^n_qubits]")
+        return torch.view_as_real(psi0.contiguous())
+
     def forward(self, theta: torch.Tensor, x: Optional[torch.Tensor], ws: torch.Tensor,
-                E: Optional[torch.Tensor] = None) -> torch.Tensor:
+                E: Optional[torch.Tensor] = None, psi0: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """psi0: initial states (complex, [batch, 2^n]); None is |0...0>."""
         self._check_inputs(theta, x)
+        p0 = self._check_psi0(psi0)
         theta = theta.contiguous()
         x = x.contiguous() if x is not None else None
         if E is None:
             E = torch.empty(self.batch, self.circuit.n_obs, dtype=self.dtype, device=theta.device)
-        fwd = qf_forward_c128 if self.c128 else qf_forward
-        fwd(self.handle, theta, x, E, ws, ws.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        if self.c128:
+            qf_forward_c128(self.handle, theta, x, p0, E, ws, ws.numel(), s)
+        else:
+            qf_forward_psi0(self.handle, theta, x, p0, E, ws, ws.numel(), s)
         return E
 
     def backward(self, theta: torch.Tensor, x: Optional[torch.Tensor], dE: torch.Tensor, ws: torch.Tensor,
-                 want_dx: bool = True):
+                 want_dx: bool = True, psi0: Optional[torch.Tensor] = None):
+        """psi0: the same initial states as the forward (None: |0...0>)."""
         self._check_inputs(theta, x)
+        p0 = self._check_psi0(psi0)
         dE = dE.contiguous().to(self.dtype)
         dtheta = torch.empty_like(theta)
         dx = torch.empty_like(x) if (want_dx and x is not None) else None
-        bwd = qf_backward_c128 if self.c128 else qf_backward
-        bwd(self.handle, theta.contiguous(), x.contiguous() if x is not None else None, dE, dtheta, dx, ws,
-            ws.numel(), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        xc = x.contiguous() if x is not None else None
+        if self.c128:
+            qf_backward_c128(self.handle, theta.contiguous(), xc, dE, dtheta, dx, ws, ws.numel(), s)
+        else:
+            qf_backward_psi0(self.handle, theta.contiguous(), xc, p0, dE, dtheta, dx, ws, ws.numel(), s)
         return dtheta, dx
 
     def __del__(self):
@@ -289,11 +321,12 @@ class CircuitFunction(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, theta, x, plan: Plan, retain_workspace: bool = False):
+    def forward(ctx, theta, x, plan: Plan, retain_workspace: bool = False, psi0=None):
         ws = plan.new_workspace(theta.device)
-        E = plan.forward(theta.detach(), x.detach() if x is not None else None, ws)
+        E = plan.forward(theta.detach(), x.detach() if x is not None else None, ws, psi0=psi0)
         ctx.plan = plan
         ctx.ws = ws
+        ctx.psi0 = psi0
         ctx.save_for_backward(theta, x if x is not None else torch.empty(0, device=theta.device))
         ctx.has_x = x is not None
         ctx.retain = bool(retain_workspace)
@@ -305,15 +338,17 @@ class CircuitFunction(torch.autograd.Function):
         x = x if ctx.has_x else None
         want_dx = ctx.has_x and ctx.needs_input_grad[1]
         dtheta, dx = ctx.plan.backward(theta.detach(), x.detach() if x is not None else None, gE, ctx.ws,
-                                       want_dx=want_dx)
+                                       want_dx=want_dx, psi0=ctx.psi0)
         if not ctx.retain:
             ctx.ws = None
-        return dtheta, dx, None, None
+            ctx.psi0 = None
+        return dtheta, dx, None, None, None
 
 
 def circuit_expectations(theta: torch.Tensor, x: Optional[torch.Tensor], plan: Plan,
-                         retain_workspace: bool = False) -> torch.Tensor:
-    return CircuitFunction.apply(theta, x, plan, retain_workspace)
+                         retain_workspace: bool = False, psi0: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """E = circuit(theta, x) from |0...0> or from the initial states psi0 (no gradient w.r.t. psi0)."""
+    return CircuitFunction.apply(theta, x, plan, retain_workspace, psi0)
 
 
 # --------------------------------------------------------------------- mixed batches

@@ -178,3 +178,32 @@ def mixed(n_circuits: int, qubits=(10, 18), layers=(50, 500), samples: int = 4, 
 def c5(n_circuits: int = 256, samples: int = 4, seed: int = 5):
     """256 circuits, qubits ~ U{10..18}, layers ~ U{50..500}, RY,RZ + ladder, 4 samples each, <Z_0>."""
     return mixed(n_circuits, (10, 18), (50, 500), samples, seed)
+
+
+@dataclasses.dataclass
+class PaperModeWorkload:
+    """The paper's own experiment shape (Sec. 4): random initial states, an HEA of
+    RX, RY, RZ layers closed into a CZ ring, and the observable (IXYZ) repeated
+    over the register."""
+    n_qubits: int
+    n_layers: int
+    gates: np.ndarray
+    theta: np.ndarray
+    psi0: np.ndarray         # complex64 [batch, 2^n], unit norm per sample
+    xmask: np.ndarray
+    zmask: np.ndarray
+
+
+def paper_mode(n_qubits: int, n_layers: int, batch: int, seed: int = 6) -> PaperModeWorkload:
+    """Seeded paper-mode inputs: theta ~ U[0, 2 pi) as float32, then psi0 with
+    independent standard normal real and imaginary parts, normalised per sample
+    (the paper does not state its distribution; this is the reading taken)."""
+    gates = hea_gates(n_qubits, n_layers, ("RX", "RY", "RZ"), encoding=False, ring=n_qubits > 2)
+    rng = np.random.default_rng(seed)
+    theta = rng.uniform(0.0, 2.0 * math.pi, n_layers * 3 * n_qubits).astype(np.float32)
+    psi = rng.standard_normal((batch, 1 << n_qubits)) + 1j * rng.standard_normal((batch, 1 << n_qubits))
+    psi /= np.linalg.norm(psi, axis=1, keepdims=True)
+    spec = ("IXYZ" * (n_qubits // 4 + 1))[:n_qubits]
+    xm, zm = pauli_string(spec)
+    return PaperModeWorkload(n_qubits, n_layers, gates, theta, psi.astype(np.complex64),
+                             np.array([xm], np.uint64), np.array([zm], np.uint64))

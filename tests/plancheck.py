@@ -56,7 +56,7 @@ def _desc(n, gates, n_params, n_inputs, zmask, xmask=None):
     return d, (gates, obs)
 
 
-def run(n, gates, theta, x, zmask, dE=None, xmask=None, **tuning):
+def run(n, gates, theta, x, zmask, dE=None, xmask=None, psi0=None, **tuning):
     theta = np.ascontiguousarray(theta, dtype=np.float32)
     x = np.ascontiguousarray(x, dtype=np.float32)
     B = x.shape[0]
@@ -68,9 +68,11 @@ def run(n, gates, theta, x, zmask, dE=None, xmask=None, **tuning):
     dx = np.zeros_like(x)
     f = ctypes.c_void_p
     dEa = None if dE is None else np.ascontiguousarray(dE, dtype=np.float32)
-    rc = lib().qfc_run(ctypes.byref(d), B, ctypes.byref(t), f(theta.ctypes.data), f(x.ctypes.data),
-                       f(dEa.ctypes.data) if dEa is not None else None, f(E.ctypes.data), f(dth.ctypes.data),
-                       f(dx.ctypes.data))
+    p0 = None if psi0 is None else np.ascontiguousarray(psi0, dtype=np.complex64)
+    rc = lib().qfc_run_psi0(ctypes.byref(d), B, ctypes.byref(t), f(theta.ctypes.data), f(x.ctypes.data),
+                            f(p0.ctypes.data) if p0 is not None else None,
+                            f(dEa.ctypes.data) if dEa is not None else None, f(E.ctypes.data), f(dth.ctypes.data),
+                            f(dx.ctypes.data))
     if rc != 0:
         raise RuntimeError(f"qfc_run: {rc} {lib().qfc_last_error().decode()}")
     return E, dth, dx

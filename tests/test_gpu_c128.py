@@ -113,7 +113,7 @@ def test_c128_and_float_paths_reject_each_other():
         qfuse.qf_forward(p64.handle, th32, x32, E32, ws, ws.numel(), s)
     assert e.value.status == 1
     with pytest.raises(qfuse.QFuseError) as e:
-        qfuse.qf_forward_c128(p32.handle, th64, x64, E64, ws, ws.numel(), s)
+        qfuse.qf_forward_c128(p32.handle, th64, x64, None, E64, ws, ws.numel(), s)
     assert e.value.status == 1
     with pytest.raises(ValueError):
         p64.forward(th32, x32, ws)

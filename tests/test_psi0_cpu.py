@@ -1,0 +1,45 @@
+"""Given initial states (the paper's random-state experiments, Sec. 4) through
+the CPU execution of the planner's programs, against the oracle started from the
+same states; the first pass reads them in place and the backward re-reads them
+for the first checkpoint segment."""
+import numpy as np
+import pytest
+
+import plancheck as pc
+from oracle.oracle import Oracle
+from paper_2603_02804_amd.workloads import draw_inputs, hea_gates, paper_mode, z_observables
+
+E_TOL, G_TOL = 1e-4, 1e-3
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a, np.float64) - b).max() / max(np.abs(b).max(), 1e-30))
+
+
+@pytest.mark.parametrize("n,L,B,tun", [
+    (13, 3, 2, {}),
+    (14, 4, 2, dict(ckpt_interval=1, micro_batch=1)),
+    (14, 4, 3, dict(store_ckpt=0, ckpt_interval=2, micro_batch=2)),
+    (8, 3, 2, dict(mode=1)),
+])
+def test_paper_mode_against_oracle(n, L, B, tun):
+    w = paper_mode(n, L, B, seed=n)
+    x = np.zeros((B, 0), np.float32)
+    dE = np.random.default_rng(n).normal(size=(B, 1))
+    E, dth, _ = pc.run(n, w.gates, w.theta, x, w.zmask, dE, xmask=w.xmask, psi0=w.psi0, **tun)
+    Eo, dtho, _ = Oracle().backward(n, w.gates, w.theta, x, w.xmask, w.zmask, dE, psi0=w.psi0)
+    assert np.abs(E - Eo).max() <= E_TOL
+    assert rel(dth, dtho) <= G_TOL
+
+
+def test_psi0_with_encoding_and_z_observables():
+    n, L, B = 13, 3, 2
+    gates = hea_gates(n, L, ("RY", "RZ"))
+    theta, x, _ = draw_inputs(17, L * 2 * n, B, n)
+    psi0 = paper_mode(n, 1, B, seed=3).psi0
+    xm, zm = z_observables([0, 12])
+    dE = np.random.default_rng(1).normal(size=(B, 2))
+    E, dth, dx = pc.run(n, gates, theta, x, zm, dE, psi0=psi0)
+    Eo, dtho, dxo = Oracle().backward(n, gates, theta, x, xm, zm, dE, psi0=psi0)
+    assert np.abs(E - Eo).max() <= E_TOL
+    assert rel(dth, dtho) <= G_TOL and rel(dx, dxo) <= G_TOL
