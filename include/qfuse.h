@@ -53,15 +53,19 @@ typedef enum {
   QF_ERR_INTERNAL = 6
 } qf_status;
 
-/* Gate kinds (Sec. 3.1): Pauli rotations and CZ. */
-typedef enum { QF_RX = 0, QF_RY = 1, QF_RZ = 2, QF_CZ = 3 } qf_gate_kind;
+/* Gate kinds (Sec. 3.1): Pauli rotations, CZ and CNOT (q0 = control, q1 =
+   target).  A CNOT is simulated as RY_t(-pi/2), CZ(c, t), RY_t(pi/2) on its
+   target t, which the planner fuses with the neighbouring rotations and
+   diagonal gates like any other gate (the paper's fused CNOT of App. B.1 moves
+   amplitudes instead). */
+typedef enum { QF_RX = 0, QF_RY = 1, QF_RZ = 2, QF_CZ = 3, QF_CNOT = 4 } qf_gate_kind;
 
 /*
  * One gate.  Layout-compatible with int32[5].
  *  - rotations: q0 = target qubit, q1 = -1; the angle is theta[theta_idx] when
  *    theta_idx >= 0, else x[b][input_idx] (an input-encoding angle, per sample);
  *    exactly one of the two indices is >= 0.
- *  - CZ: q0 != q1, both in [0, n_qubits); theta_idx = input_idx = -1.
+ *  - CZ, CNOT: q0 != q1, both in [0, n_qubits); theta_idx = input_idx = -1.
  * An angle index used by several gates receives the sum of their gradients.
  */
 typedef struct { int32_t kind, q0, q1, theta_idx, input_idx; } qf_gate;

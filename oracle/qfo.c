@@ -14,6 +14,9 @@
  *  - A single-qubit gate u on target t updates every pair of amplitudes whose
  *    indices differ only in bit t: (a0, a1) <- u (a0, a1)  (Sec. 3.1).
  *  - CZ(c, t) negates the amplitudes whose bits c and t are both 1 (Sec. 3.1).
+ *  - CNOT(c, t) flips bit t of every basis state whose bit c is 1: it swaps the
+ *    amplitudes x and x ^ 2^t for every x with bit c set (Sec. 3.1, the fused
+ *    CNOT of App. B.1 is this permutation of the state's indices).
  *  - Pauli rotations u(phi) = cos(phi/2) I - i sin(phi/2) P, with derivative
  *    du/dphi = -1/2 sin(phi/2) I - i/2 cos(phi/2) P  (Sec. 3.3, step 2).
  *  - Expectation E = <psi_M| O |psi_M> (Sec. 2.1) for Pauli strings O given by
@@ -32,7 +35,8 @@
  *   mode 1: store every psi_j during the forward sweep (small cases only).
  *
  * Gate encoding (this file's own): int32 quintuples
- *   { kind, q0, q1, theta_idx, input_idx }, kind 0=RX 1=RY 2=RZ 3=CZ.
+ *   { kind, q0, q1, theta_idx, input_idx }, kind 0=RX 1=RY 2=RZ 3=CZ 4=CNOT
+ *   (q0 = control, q1 = target).
  * A rotation takes its angle from theta[theta_idx] if theta_idx >= 0, else from
  * x[b][input_idx].  Gradients of an angle used by several gates are summed;
  * dtheta is summed over the batch, dx is per sample.
@@ -47,7 +51,7 @@
 #include <omp.h>
 #endif
 
-enum { QFO_RX = 0, QFO_RY = 1, QFO_RZ = 2, QFO_CZ = 3 };
+enum { QFO_RX = 0, QFO_RY = 1, QFO_RZ = 2, QFO_CZ = 3, QFO_CNOT = 4 };
 
 typedef struct { double re, im; } cplx;
 
@@ -133,6 +137,19 @@ static void apply_cz(cplx* psi, int n, int c, int t) {
     if ((i & mc) && (i & mt)) psi[i] = c_scale(psi[i], -1.0);
 }
 
+/* CNOT: swap the amplitudes of x and x ^ 2^t wherever bit c of x is 1. */
+static void apply_cnot(cplx* psi, int n, int c, int t) {
+  int64_t dim = (int64_t)1 << n, i;
+  int64_t mc = (int64_t)1 << c, mt = (int64_t)1 << t;
+#pragma omp parallel for schedule(static) if (n >= 16)
+  for (i = 0; i < dim; ++i)
+    if ((i & mc) && !(i & mt)) {
+      cplx a = psi[i];
+      psi[i] = psi[i | mt];
+      psi[i | mt] = a;
+    }
+}
+
 /* Re <lam| (d applied on bit t) |psi> */
 static double grad_term(const cplx* lam, const cplx* psi, int n, int t, mat2 d) {
   int64_t dim = (int64_t)1 << n, step = (int64_t)1 << t, i;
@@ -178,9 +195,9 @@ static int validate(int n, int n_gates, const int32_t* gates, int n_params, int 
   if (n < 1 || n > 30 || n_gates < 0) return 1;
   for (j = 0; j < n_gates; ++j) {
     const int32_t* g = gates + 5 * j;
-    if (g[0] < 0 || g[0] > 3) return 2;
+    if (g[0] < 0 || g[0] > 4) return 2;
     if (g[1] < 0 || g[1] >= n) return 3;
-    if (g[0] == QFO_CZ) {
+    if (g[0] == QFO_CZ || g[0] == QFO_CNOT) {
       if (g[2] < 0 || g[2] >= n || g[2] == g[1]) return 4;
     } else {
       if ((g[3] >= 0) == (g[4] >= 0)) return 5;
@@ -198,6 +215,7 @@ static void forward_one(cplx* psi, int n, int n_gates, const int32_t* gates,
   for (j = 0; j < n_gates; ++j) {
     const int32_t* g = gates + 5 * j;
     if (g[0] == QFO_CZ) apply_cz(psi, n, g[1], g[2]);
+    else if (g[0] == QFO_CNOT) apply_cnot(psi, n, g[1], g[2]);
     else apply_1q(psi, n, g[1], rot(g[0], angle_of(g, theta, xb)));
     if (store) memcpy(store[j + 1], psi, sizeof(cplx) << n);
   }
@@ -325,6 +343,10 @@ int qfo_backward(int n, int n_gates, const int32_t* gates, int n_params, const d
         /* CZ is real and self-adjoint; it has no parameter */
         if (mode == 0) apply_cz(psi, n, g[1], g[2]);
         apply_cz(lam, n, g[1], g[2]);
+      } else if (g[0] == QFO_CNOT) {
+        /* a permutation that is its own inverse; no parameter */
+        if (mode == 0) apply_cnot(psi, n, g[1], g[2]);
+        apply_cnot(lam, n, g[1], g[2]);
       } else {
         double phi = angle_of(g, theta, xb);
         mat2 u = rot(g[0], phi);

@@ -237,7 +237,10 @@ __device__ __forceinline__ const float* run_coef(const KArgs& A, int ref, int sa
 }
 
 __device__ __forceinline__ float2 event_coef(const KArgs& A, int ref, int sample) {
-  const float* p = ref >= 0 ? A.ev_sh + 2 * (size_t)ref : A.ev_ps + 2 * ((size_t)sample * A.n_evps + (-1 - ref));
+  // shared row ref >= 0, or per-sample row -1 - ref: selected without a branch
+  const bool sh = ref >= 0;
+  const float* base = sh ? A.ev_sh : A.ev_ps + 2 * (size_t)sample * A.n_evps;
+  const float* p = base + 2 * (size_t)(sh ? ref : -1 - ref);
   return make_float2(cld(p), cld(p + 1));
 }
 
@@ -270,6 +273,10 @@ constexpr int pass_min_waves() {
   return R <= 4 ? 3 : 1;
 }
 
+// Backward pass workgroups: one functional partial sum per wave, slot and Pauli
+// (dynamic LDS after the static tile).
+extern __shared__ float qf_pass_part[];
+
 // Per-workgroup context of a fused pass: the uniform launch arguments, the
 // thread's coordinates and the bodies of the ops.  The register arrays and the
 // pending phase are passed by reference, so that they stay in registers.
@@ -279,7 +286,6 @@ struct PassCtx {
   static constexpr int WAVES = NT / 64;
   KArgs A;
   float2* lds;
-  float* part;
   ThreadBits<NT> tbase;
   uint32_t tlog;
   bool active;
@@ -365,7 +371,24 @@ struct PassCtx {
   const float g = f ? -1.f : 1.f;
   ph.x *= g;
   ph.y *= g;
-  for (int i = 0; i < npev; ++i) {
+  // phase events in groups of four: the records, then the coefficients, are
+  // loaded together, so that each group waits on scalar memory twice
+  int i = 0;
+  for (; i + 4 <= npev; i += 4) {
+    PhaseEv e[4];
+    float2 w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = ld_pev(A.pev + pev0 + i + k);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = event_coef(A, e[k].ref, sample);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const bool conj = (((x >> e[k].q) & 1u) != 0u) != BWD;
+      if (conj) w[k].y = -w[k].y;
+      cmul_in(ph, w[k]);
+    }
+  }
+  for (; i < npev; ++i) {
     const PhaseEv e = ld_pev(A.pev + pev0 + i);
     float2 w = event_coef(A, e.ref, sample);
     const bool conj = (((x >> e.q) & 1u) != 0u) != BWD;
@@ -406,6 +429,10 @@ struct PassCtx {
       // functionals of every register bit; entry j (register bit j) names the
       // run's slot, or -1 when the bit holds no run of this group
       const FuncEntry* fe = A.funcs + first;
+      // the slots of the R register bits, read as uniform scalars
+      int sl[R];
+#pragma unroll
+      for (int j = 0; j < R; ++j) sl[j] = cld(&fe[j].slot);
       float v[16];
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = 0.f;
@@ -419,8 +446,12 @@ struct PassCtx {
       const int idx = (lane >> 2) & 15;
       if ((lane & 3) == 0 && idx < 3 * R) {
         const int e = idx / 3, pq = idx - 3 * e;
-        const int slot = fe[e].slot;
+        int slot = sl[0];
+#pragma unroll
+        for (int j = 1; j < R; ++j) slot = (e == j) ? sl[j] : slot;
         if (slot >= 0) {
+          // through an LDS-typed pointer
+          __attribute__((address_space(3))) float* part = (__attribute__((address_space(3))) float*)qf_pass_part;
           part[wave * 3 * n_slots + 3 * slot + pq] = sum;
         }
       }
@@ -432,8 +463,6 @@ template <int R, int NT, bool BWD>
 __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
   // the tile: a static array, so that its base folds into the LDS offsets
   __shared__ float2 lds[(1 << R) * NT];
-  // backward: per-wave functional partial sums (dynamic size)
-  extern __shared__ float lds_part[];
   constexpr int NA = 1 << R;
   constexpr int WAVES = NT / 64;
   const int t = threadIdx.x;
@@ -468,7 +497,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
   // multiplies psi (and, in the backward, lambda as well)
   float2 ph = make_float2(1.f, 0.f);
 
-  const PassCtx<R, NT, BWD> cx{A, lds, lds_part, tbase, tlog, active, sample, lane, wave, n_slots};
+  const PassCtx<R, NT, BWD> cx{A, lds, tbase, tlog, active, sample, lane, wave, n_slots};
 
   // the next op record is fetched while the current one executes
   Op next = ld_op(A.ops);
@@ -648,7 +677,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
     // one partial sum per tile and functional: add the waves' sums
     if (n_slots > 0) {
       __syncthreads();
-      const float* part = lds_part;
+      const float* part = qf_pass_part;
       for (int i = t; i < 3 * n_slots; i += NT) {
         float acc = 0.f;
 #pragma unroll

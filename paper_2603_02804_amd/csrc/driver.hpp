@@ -115,7 +115,7 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
   std::vector<std::pair<int, int>> th, in;
   for (size_t g = 0; g < S.gates.size(); ++g) {
     if (S.gates[g].theta_idx >= 0) th.push_back({S.gates[g].theta_idx, (int)g});
-    else in.push_back({S.gates[g].input_idx, (int)g});
+    else if (S.gates[g].input_idx >= 0) in.push_back({S.gates[g].input_idx, (int)g});
   }
   build_csr(C.P, th, &c.th_ref_begin, &c.th_refs);
   build_csr(C.F, in, &c.in_ref_begin, &c.in_refs);

@@ -58,6 +58,7 @@ inline qf_status upload_plan(const PlanCore& c, DevPlan* d, std::string* msg) {
   push_table(blob, o, c.S.epochs);       // 24
   push_table(blob, o, c.S.phas);         // 25
   push_table(blob, o, pauli_table(c));   // 26
+  push_table(blob, o, c.C.consts);       // 27
   d->bytes = blob.size();
   if (hipMalloc(&d->blob, d->bytes) != hipSuccess) {
     if (msg) *msg = "hipMalloc of plan tables failed";
@@ -98,6 +99,7 @@ inline qf_status upload_plan(const PlanCore& c, DevPlan* d, std::string* msg) {
   p.epochs = (const EpochRec*)(b + o[24]);
   p.phas = (const PhaEntry*)(b + o[25]);
   p.pauli = (const PauliRec*)(b + o[26]);
+  t.consts = (const double*)(b + o[27]);
   return QF_OK;
 }
 

@@ -28,6 +28,7 @@ struct Tabs {
   const int32_t* in_refs;
   const int32_t* pass_run_begin;
   const int32_t* pass_runs;
+  const double* consts;         // fixed angles of internal gates (lowered CNOT)
 };
 
 struct PlanPtrs {

@@ -25,13 +25,13 @@ qf_status validate_circuit(const qf_circuit_desc* d, std::string* msg) {
   for (int64_t j = 0; j < d->n_gates; ++j) {
     const qf_gate& g = d->gates[j];
     const std::string at = " (gate " + std::to_string(j) + ")";
-    if (g.kind < QF_RX || g.kind > QF_CZ) return fail(QF_ERR_INVALID_ARG, "unknown gate kind" + at);
+    if (g.kind < QF_RX || g.kind > QF_CNOT) return fail(QF_ERR_INVALID_ARG, "unknown gate kind" + at);
     if (g.q0 < 0 || g.q0 >= n) return fail(QF_ERR_INVALID_ARG, "qubit out of range" + at);
-    if (g.kind == QF_CZ) {
-      if (g.q1 < 0 || g.q1 >= n) return fail(QF_ERR_INVALID_ARG, "CZ partner out of range" + at);
-      if (g.q1 == g.q0) return fail(QF_ERR_INVALID_ARG, "CZ on a single qubit" + at);
+    if (g.kind == QF_CZ || g.kind == QF_CNOT) {
+      if (g.q1 < 0 || g.q1 >= n) return fail(QF_ERR_INVALID_ARG, "two-qubit gate partner out of range" + at);
+      if (g.q1 == g.q0) return fail(QF_ERR_INVALID_ARG, "two-qubit gate on a single qubit" + at);
       if (g.theta_idx != -1 || g.input_idx != -1)
-        return fail(QF_ERR_INVALID_ARG, "CZ carries no angle" + at);
+        return fail(QF_ERR_INVALID_ARG, "CZ and CNOT carry no angle" + at);
     } else {
       if ((g.theta_idx >= 0) == (g.input_idx >= 0))
         return fail(QF_ERR_INVALID_ARG, "rotation needs exactly one angle source" + at);
@@ -46,6 +46,30 @@ qf_status validate_circuit(const qf_circuit_desc* d, std::string* msg) {
       return fail(QF_ERR_INVALID_ARG, "observable acts outside the register");
   }
   return QF_OK;
+}
+
+void circuit_from_desc(const qf_circuit_desc* d, Circuit* C) {
+  C->n = d->n_qubits;
+  C->P = d->n_params;
+  C->F = d->n_inputs;
+  C->K = d->n_obs;
+  C->gates.clear();
+  C->consts.clear();
+  C->obs.assign(d->obs, d->obs + d->n_obs);
+  const double half_pi = 1.5707963267948966;
+  for (int64_t j = 0; j < d->n_gates; ++j) {
+    const qf_gate& g = d->gates[j];
+    if (g.kind != QF_CNOT) {
+      C->gates.push_back(g);
+      continue;
+    }
+    const int t = g.q1;
+    C->consts.push_back(-half_pi);
+    C->gates.push_back({QF_RY, t, -1, -1 - (int)C->consts.size(), -1});
+    C->gates.push_back({QF_CZ, g.q0, t, -1, -1});
+    C->consts.push_back(half_pi);
+    C->gates.push_back({QF_RY, t, -1, -1 - (int)C->consts.size(), -1});
+  }
 }
 
 namespace {

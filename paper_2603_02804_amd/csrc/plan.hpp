@@ -21,9 +21,18 @@ namespace qf {
 
 struct Circuit {
   int n = 0, P = 0, F = 0, K = 0;
-  std::vector<qf_gate> gates;
+  std::vector<qf_gate> gates;       // CNOT lowered (see circuit_from_desc)
   std::vector<qf_pauli> obs;
+  std::vector<double> consts;       // fixed angles of internal gates: theta_idx = -2 - index
 };
+
+// Internal gate with a fixed angle: theta_idx encodes the constant's index.
+inline bool gate_is_const(const qf_gate& g) { return g.theta_idx <= -2; }
+
+// Copies a validated description.  CNOT(c, t) becomes RY_t(-pi/2), CZ(c, t),
+// RY_t(pi/2) (since H = RY(pi/2) Z and Z commutes with CZ, H CZ H = CNOT), so
+// that the planner fuses it like any rotation and diagonal gate.
+void circuit_from_desc(const qf_circuit_desc* d, Circuit* C);
 
 // Returns QF_OK or a status with a message; checks every index and size.
 qf_status validate_circuit(const qf_circuit_desc* d, std::string* msg);

@@ -107,6 +107,7 @@ struct CpuExec {
   qf_status status() const { return QF_OK; }
 
   double angle(const GateRec& g, int sample) const {
+    if (g.theta_idx <= -2) return c.C.consts[-2 - g.theta_idx];
     return g.theta_idx >= 0 ? (double)theta[g.theta_idx] : (double)x[(int64_t)sample * c.C.F + g.input_idx];
   }
   M2 run_matrix(int r, int sample) const {
@@ -722,9 +723,7 @@ int qfc_run_psi0(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tu
     qf_status st = validate_circuit(desc, &msg);
     if (st != QF_OK) { g_err = msg; return st; }
     Circuit C;
-    C.n = desc->n_qubits; C.P = desc->n_params; C.F = desc->n_inputs; C.K = desc->n_obs;
-    C.gates.assign(desc->gates, desc->gates + desc->n_gates);
-    C.obs.assign(desc->obs, desc->obs + desc->n_obs);
+    circuit_from_desc(desc, &C);
     Tuning T;
     if (tuning) {
       T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
@@ -763,9 +762,7 @@ int qfc_stats(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tunin
   qf_status st = validate_circuit(desc, &msg);
   if (st != QF_OK) { g_err = msg; return st; }
   Circuit C;
-  C.n = desc->n_qubits; C.P = desc->n_params; C.F = desc->n_inputs; C.K = desc->n_obs;
-  C.gates.assign(desc->gates, desc->gates + desc->n_gates);
-  C.obs.assign(desc->obs, desc->obs + desc->n_obs);
+  circuit_from_desc(desc, &C);
   Tuning T;
   if (tuning) {
     T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
@@ -804,9 +801,7 @@ int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, i
       qf_status st = validate_circuit(descs[i], &msg);
       if (st != QF_OK) { g_err = msg; return st; }
       Circuit C;
-      C.n = descs[i]->n_qubits; C.P = descs[i]->n_params; C.F = descs[i]->n_inputs; C.K = descs[i]->n_obs;
-      C.gates.assign(descs[i]->gates, descs[i]->gates + descs[i]->n_gates);
-      C.obs.assign(descs[i]->obs, descs[i]->obs + descs[i]->n_obs);
+      circuit_from_desc(descs[i], &C);
       pcs.emplace_back(new PlanCore);
       st = build_plan_core(C, samples[i], T, pcs.back().get(), &msg);
       if (st != QF_OK) { g_err = msg; return st; }

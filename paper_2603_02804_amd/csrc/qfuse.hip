@@ -554,12 +554,7 @@ qf_status qf_circuit_create(const qf_circuit_desc* desc, qf_circuit** out) {
   if (st != QF_OK) return fail(st, msg);
   try {
     qf_circuit* c = new qf_circuit;
-    c->c.n = desc->n_qubits;
-    c->c.P = desc->n_params;
-    c->c.F = desc->n_inputs;
-    c->c.K = desc->n_obs;
-    c->c.gates.assign(desc->gates, desc->gates + desc->n_gates);
-    c->c.obs.assign(desc->obs, desc->obs + desc->n_obs);
+    circuit_from_desc(desc, &c->c);
     *out = c;
   } catch (...) {
     return fail(QF_ERR_OOM, "host allocation failed");

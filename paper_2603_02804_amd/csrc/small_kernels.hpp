@@ -68,7 +68,9 @@ __device__ inline D2 d2_dag(const D2& a) {
 }
 
 template <class Real>
-__device__ inline double gate_angle(const GateRec& g, const Real* theta, const Real* x, int F, int sample) {
+__device__ inline double gate_angle(const Tabs& T, const GateRec& g, const Real* theta, const Real* x, int F,
+                                    int sample) {
+  if (g.theta_idx <= -2) return T.consts[-2 - g.theta_idx];   // fixed angle of an internal gate
   return g.theta_idx >= 0 ? (double)theta[g.theta_idx] : (double)x[(size_t)sample * F + g.input_idx];
 }
 
@@ -107,7 +109,7 @@ __device__ inline D2 run_matrix(const Tabs& T, const RunRec& rr, const Real* the
   D2 U = d2_eye();
   for (int i = 0; i < rr.gate_count; ++i) {
     const GateRec g = T.gates[T.run_gates[rr.gate_begin + i]];
-    U = d2_mul(d2_rot(g.kind, gate_angle(g, theta, x, F, sample)), U);
+    U = d2_mul(d2_rot(g.kind, gate_angle(T, g, theta, x, F, sample)), U);
   }
   return U;
 }
@@ -204,7 +206,7 @@ __device__ inline void run_grads(const Tabs& T, int r, const Real* theta, const 
     const D2 G = d2_mul(d2_mul(K, d2_pauli(g.kind)), d2_dag(K));
     const double gr = zr * G.r[2] - zi * G.i[2], gi = zr * G.i[2] + zi * G.r[2];
     Grow[g.out_idx] = (Real)(0.5 * (gr * fx + gi * fy + G.r[0] * fz));
-    K = d2_mul(K, d2_rot(g.kind, gate_angle(g, theta, x, F, sample)));
+    K = d2_mul(K, d2_rot(g.kind, gate_angle(T, g, theta, x, F, sample)));
   }
 }
 

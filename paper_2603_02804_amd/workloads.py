@@ -12,7 +12,7 @@ is available as an option.  Inputs are angle-encoded by RY(x_q) on qubit q befor
 the first layer.
 
 Gate rows are int32 quintuples ``(kind, q0, q1, theta_idx, input_idx)`` with
-kind 0=RX, 1=RY, 2=RZ, 3=CZ.  A rotation takes its angle from ``theta[theta_idx]``
+kind 0=RX, 1=RY, 2=RZ, 3=CZ, 4=CNOT (q0 control, q1 target).  A rotation takes its angle from ``theta[theta_idx]``
 when ``theta_idx >= 0`` and from ``x[b, input_idx]`` otherwise.
 
 Random draws follow one fixed recipe: ``numpy.random.default_rng(seed)``, then
@@ -26,13 +26,14 @@ from typing import Sequence
 
 import numpy as np
 
-RX, RY, RZ, CZ = 0, 1, 2, 3
+RX, RY, RZ, CZ, CNOT = 0, 1, 2, 3, 4
 _ROT_CODES = {"RX": RX, "RY": RY, "RZ": RZ}
 
 
 def hea_gates(n_qubits: int, n_layers: int, rotations: Sequence[str] = ("RY", "RZ"),
-              encoding: bool = True, ring: bool = False) -> np.ndarray:
-    """Gate list of an HEA with optional RY input encoding.
+              encoding: bool = True, ring: bool = False, entangler: int = CZ) -> np.ndarray:
+    """Gate list of an HEA with optional RY input encoding; the entangling ladder
+    (or ring) uses CZ, or CNOT(q -> q+1) with ``entangler=CNOT``.
 
     Parameter index of layer l, rotation r, qubit q: ``l * (R * n) + r * n + q``.
     """
@@ -47,9 +48,9 @@ def hea_gates(n_qubits: int, n_layers: int, rotations: Sequence[str] = ("RY", "R
             for q in range(n_qubits):
                 rows.append((code, q, -1, layer * R * n_qubits + r * n_qubits + q, -1))
         for q in range(n_qubits - 1):
-            rows.append((CZ, q, q + 1, -1, -1))
+            rows.append((entangler, q, q + 1, -1, -1))
         if ring and n_qubits > 2:
-            rows.append((CZ, n_qubits - 1, 0, -1, -1))
+            rows.append((entangler, n_qubits - 1, 0, -1, -1))
     return np.asarray(rows, dtype=np.int32).reshape(-1, 5)
 
 

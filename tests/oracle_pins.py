@@ -14,6 +14,8 @@ Sources of truth (none is the oracle itself):
   P6  parameter-shift rule, exact for exp(-i phi P / 2)                    (Sec. 1)
   P7  un-apply backward vs store-all backward vs central finite differences (Sec. 2.2)
   P9  Pauli-string expectation vs the dense Pauli product                 (App. B.2)
+  P10 CNOT: the truth table on basis states, the Bell-state closed forms and the
+      parameter shift through CNOT ladders (P5 and P6 also draw CNOT gates)
 """
 from __future__ import annotations
 
@@ -21,7 +23,7 @@ import math
 
 import numpy as np
 
-from paper_2603_02804_amd.workloads import CZ, RX, RY, RZ, hea_gates, pauli_string, z_observables
+from paper_2603_02804_amd.workloads import CNOT, CZ, RX, RY, RZ, hea_gates, pauli_string, z_observables
 
 I2 = np.eye(2, dtype=np.complex128)
 PX = np.array([[0, 1], [1, 0]], dtype=np.complex128)
@@ -152,6 +154,15 @@ def _cz_dense(n, a, b):
     return np.diag(d)
 
 
+def _cnot_dense(n, c, t):
+    """The permutation matrix of CNOT: |x> -> |x ^ 2^t> where bit c of x is 1."""
+    m = np.zeros((1 << n, 1 << n), dtype=np.complex128)
+    for i in range(1 << n):
+        j = i ^ (1 << t) if (i >> c) & 1 else i
+        m[j, i] = 1
+    return m
+
+
 def dense_state(n, gates, theta, xb, psi0=None):
     psi = np.zeros(1 << n, dtype=np.complex128)
     psi[0] = 1
@@ -161,6 +172,8 @@ def dense_state(n, gates, theta, xb, psi0=None):
     for (k, q0, q1, t, f) in gates:
         if k == CZ:
             G = _cz_dense(n, q0, q1)
+        elif k == CNOT:
+            G = _cnot_dense(n, q0, q1)
         else:
             phi = theta[t] if t >= 0 else xb[f]
             G = _embed(n, q0, _u_dense(k, phi))
@@ -174,11 +187,11 @@ def pin_p5_dense(orc):
         rows = []
         t = 0
         for _ in range(4 * n + 3):
-            k = int(rng.integers(0, 4)) if n > 1 else int(rng.integers(0, 3))
+            k = int(rng.integers(0, 5)) if n > 1 else int(rng.integers(0, 3))
             q0 = int(rng.integers(0, n))
-            if k == CZ:
+            if k in (CZ, CNOT):
                 q1 = int((q0 + 1 + rng.integers(0, n - 1)) % n)
-                rows.append(_g(CZ, q0, q1))
+                rows.append(_g(k, q0, q1))
             elif rng.random() < 0.3:
                 rows.append(_g(k, q0, f=int(rng.integers(0, n))))
             else:
@@ -292,5 +305,50 @@ def pin_p9_pauli_expectation(orc, n=5):
         np.testing.assert_allclose(d0[p], fd, atol=1e-8)
 
 
+# ---------------------------------------------------------------- P10
+def pin_p10_cnot(orc):
+    """CNOT truth table; RY(a) on the control, then CNOT(0 -> 1): <Z_1> = cos a, <Z_0 Z_1> = 1,
+    <X_0 X_1> = sin a; a parameter-shift check through a CNOT ladder."""
+    n = 3
+    for c, t in ((0, 1), (1, 0), (2, 0), (0, 2)):
+        for basis in range(1 << n):
+            # prepare |basis> with RX(pi) flips, then CNOT
+            rows = [_g(RX, q, t=0) for q in range(n) if (basis >> q) & 1] + [_g(CNOT, c, t)]
+            _, psi = orc.forward(n, _gates(rows), np.array([math.pi]), np.zeros((1, 0)),
+                                 np.zeros(1, np.uint64), np.array([1], np.uint64), return_state=True)
+            out = basis ^ (1 << t) if (basis >> c) & 1 else basis
+            assert abs(abs(psi[0][out]) - 1.0) < 1e-12
+    for a in (0.3, 1.1, 2.9):
+        gates = _gates([_g(RY, 0, t=0), _g(CNOT, 0, 1)])
+        E = _E(orc, 2, gates, np.array([a]), np.zeros((1, 0)),
+               [pauli_string("ZI"), pauli_string("ZZ"), pauli_string("XX"), pauli_string("IZ")])
+        np.testing.assert_allclose(E[0], [math.cos(a), 1.0, math.sin(a), math.cos(a)], atol=1e-12)
+    # parameter shift through a CNOT ladder, theta and x angles
+    nq, L = 4, 2
+    rows = [_g(RY, q, f=q) for q in range(nq)]
+    t = 0
+    for _ in range(L):
+        for q in range(nq):
+            rows.append(_g(RY, q, t=t))
+            t += 1
+        for q in range(nq - 1):
+            rows.append(_g(CNOT, q, q + 1))
+    gates = _gates(rows)
+    rng = np.random.default_rng(10)
+    theta = rng.uniform(0, 2 * math.pi, t)
+    x = rng.uniform(-math.pi, math.pi, (1, nq))
+    xm, zm = pauli_string("IIXZ")
+    dE = np.array([[1.0]])
+    _, dth, dx = orc.backward(nq, gates, theta, x, np.array([xm], np.uint64), np.array([zm], np.uint64), dE)
+    for p in range(t):
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += math.pi / 2
+        tm[p] -= math.pi / 2
+        ep = orc.forward(nq, gates, tp, x, np.array([xm], np.uint64), np.array([zm], np.uint64))[0, 0]
+        em = orc.forward(nq, gates, tm, x, np.array([xm], np.uint64), np.array([zm], np.uint64))[0, 0]
+        assert abs(dth[p] - (ep - em) / 2) < 1e-10
+
+
 ALL_PINS = [pin_p1_single_qubit, pin_p2_two_qubit, pin_p3_zero_angles, pin_p4_norm,
-            pin_p5_dense, pin_p6_parameter_shift, pin_p7_backward_modes, pin_p9_pauli_expectation]
+            pin_p5_dense, pin_p6_parameter_shift, pin_p7_backward_modes, pin_p9_pauli_expectation,
+            pin_p10_cnot]

@@ -80,6 +80,10 @@ RX, RY, RZ, CZ = 0, 1, 2, 3
     (2, [[CZ, 0, 0, -1, -1]], 1, 0, (1,), None, INVALID),               # CZ on one qubit
     (2, [[CZ, 0, 2, -1, -1]], 1, 0, (1,), None, INVALID),               # CZ partner out of range
     (2, [[CZ, 0, 1, 0, -1]], 1, 0, (1,), None, INVALID),                # CZ with an angle
+    (2, [[4, 1, 0, -1, -1]], 1, 0, (1,), None, QF_OK),                  # CNOT 1 -> 0
+    (2, [[4, 1, 1, -1, -1]], 1, 0, (1,), None, INVALID),                # CNOT on one qubit
+    (2, [[4, 0, 1, 0, -1]], 1, 0, (1,), None, INVALID),                 # CNOT with an angle
+    (2, [[5, 0, 1, -1, -1]], 1, 0, (1,), None, INVALID),                # unknown two-qubit kind
     (2, [[RY, 0, -1, 0, 0]], 1, 1, (1,), None, INVALID),                # two angle sources
     (2, [[RY, 0, -1, -1, -1]], 1, 0, (1,), None, INVALID),              # no angle source
     (2, [[RY, 0, -1, 1, -1]], 1, 0, (1,), None, INVALID),               # theta_idx >= n_params

@@ -67,6 +67,10 @@ MUTANTS = [
      "dx[(int64_t)b * n_inputs + g[4]] = gr;", None),
     ("input_angle_from_theta", "return g[3] >= 0 ? theta[g[3]] : xb[g[4]];",
      "return g[3] >= 0 ? theta[g[3]] : theta[g[4]];", None),
+    ("cnot_on_control_clear", "if ((i & mc) && !(i & mt)) {", "if (!(i & mc) && !(i & mt)) {", None),
+    ("cnot_control_target_swapped", "else if (g[0] == QFO_CNOT) apply_cnot(psi, n, g[1], g[2]);",
+     "else if (g[0] == QFO_CNOT) apply_cnot(psi, n, g[2], g[1]);", None),
+    ("lambda_skips_cnot", "        apply_cnot(lam, n, g[1], g[2]);\n", "", None),
     ("batch_sum_first_sample_only", "for (b = 0; b < B; ++b) acc += gth[(int64_t)b * n_params + p];",
      "for (b = 0; b < 1; ++b) acc += gth[(int64_t)b * n_params + p];", None),
 ]
