@@ -383,16 +383,15 @@ struct PassCtx {
     for (int k = 0; k < 4; ++k) w[k] = event_coef(A, e[k].ref, sample);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const bool conj = (((x >> e[k].q) & 1u) != 0u) != BWD;
-      if (conj) w[k].y = -w[k].y;
+      // conjugate where the event's qubit is 1 (0 in the backward): sign-bit XOR
+      w[k].y = __uint_as_float(__float_as_uint(w[k].y) ^ (((x >> e[k].q) << 31) ^ (BWD ? 0x80000000u : 0u)));
       cmul_in(ph, w[k]);
     }
   }
   for (; i < npev; ++i) {
     const PhaseEv e = ld_pev(A.pev + pev0 + i);
     float2 w = event_coef(A, e.ref, sample);
-    const bool conj = (((x >> e.q) & 1u) != 0u) != BWD;
-    if (conj) w.y = -w.y;
+    w.y = __uint_as_float(__float_as_uint(w.y) ^ (((x >> e.q) << 31) ^ (BWD ? 0x80000000u : 0u)));
     cmul_in(ph, w);
   }
   }
