@@ -218,8 +218,12 @@ def main() -> int:
         torch.cuda.synchronize()
         pg_s = time.perf_counter() - t0
         pg_value = nb / pg_s
+        pgi = pg_plan.info
+        pg_gbs = (pgi.fwd_bytes_per_sample + pgi.bwd_bytes_per_sample) * pg_value / 1e9
         out["per_gate"] = {"value": round(pg_value, 3), "unit": "samples/s", "sample": f"{nb} samples, full depth",
-                           "speedup_fused": round(value / pg_value, 2)}
+                           "speedup_fused": round(value / pg_value, 2),
+                           # the unfused kernels are HBM-bound: their algorithmic bytes over time
+                           "hbm_gbs": round(pg_gbs, 1), "hbm_frac": round(pg_gbs / PEAK_HBM_GBS, 4)}
         del ws
         # CPU oracle on the host cores: one sample, the first L layers, extrapolated in depth
         from oracle.oracle import Oracle, loss_and_grad_E

@@ -31,8 +31,8 @@ TUNED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_co
 
 # (tile qubits, register qubits) shapes with compiled kernels
 TILE_SHAPES = ((12, 4), (13, 5), (11, 4))
-FUSION_DEPTHS = (4, 8, 12, 16)
-MICRO_BATCHES = (8, 16, 32)
+FUSION_DEPTHS = (4, 6, 8, 10, 12, 16)
+MICRO_BATCHES = (8, 16, 32, 64)
 
 
 def paper_memory_bytes(stored_per_layer: float, d: int, b: float, m_sv: int) -> float:
