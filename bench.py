@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--micro-batch", type=int, default=0)
     ap.add_argument("--tile-qubits", type=int, default=0)
     ap.add_argument("--reg-qubits", type=int, default=0)
+    ap.add_argument("--epoch-fill", type=int, default=0,
+                    help="end-of-pass epochs with fewer runs wait for the next pass (0: register qubits, -1: none)")
     ap.add_argument("--no-baselines", action="store_true", help="skip the per-gate and CPU baselines")
     ap.add_argument("--no-autotune", action="store_true", help="ignore the cached autotuned configuration")
     ap.add_argument("--pg-samples", type=int, default=8)
@@ -109,9 +111,9 @@ def main() -> int:
 
     tun = qfuse.make_tuning(fusion_depth=args.fusion_depth, ckpt_interval=args.ckpt_interval,
                             micro_batch=args.micro_batch, tile_qubits=args.tile_qubits,
-                            reg_qubits=args.reg_qubits)
+                            reg_qubits=args.reg_qubits, epoch_fill=args.epoch_fill)
     tuning_src = "flags" if any((args.fusion_depth, args.ckpt_interval, args.micro_batch, args.tile_qubits,
-                                 args.reg_qubits)) else "default"
+                                 args.reg_qubits, args.epoch_fill)) else "default"
     if tuning_src == "default" and not args.no_autotune:
         from paper_2603_02804_amd import autotune
         cached = autotune.cached_tuning(w.n_qubits, w.gates, w.n_obs, B, autotune.device_key(dev))
@@ -188,7 +190,8 @@ def main() -> int:
                                f"{w.n_params} angles, RY encoding of 20 features, <Z_0..Z_9> -> 10-class CE",
                    "batch": B, "micro_batch": info.micro_batch, "tile_qubits": info.tile_qubits,
                    "reg_qubits": info.reg_qubits, "fusion_depth": info.fusion_depth, "fused_passes": info.fused_passes,
-                   "ckpt_interval": info.ckpt_interval, "segments": info.segments, "tuning": tuning_src},
+                   "ckpt_interval": info.ckpt_interval, "segments": info.segments, "epoch_fill": info.epoch_fill,
+                   "tuning": tuning_src},
         "roofline": roofline,
         "hbm": {"gbs": round(hbm_gbs, 1), "frac": round(hbm_gbs / PEAK_HBM_GBS, 4),
                 "bytes_per_sample": info.fwd_bytes_per_sample + info.bwd_bytes_per_sample},
@@ -276,15 +279,16 @@ def bench_paper(args, dev) -> int:
     psi0 /= torch.linalg.vector_norm(psi0, dim=1, keepdim=True)
     xm, zm = pauli_string(("IXYZ" * 5)[:n])
     circ = qfuse.Circuit(n, gates, L * 3 * n, 0, [zm], [xm])
-    tun = qfuse.make_tuning(micro_batch=args.micro_batch or 32, fusion_depth=args.fusion_depth,
+    tun = qfuse.make_tuning(micro_batch=args.micro_batch or 128, fusion_depth=args.fusion_depth,
                             ckpt_interval=args.ckpt_interval, tile_qubits=args.tile_qubits,
-                            reg_qubits=args.reg_qubits)
+                            reg_qubits=args.reg_qubits, epoch_fill=args.epoch_fill)
     probe = qfuse.Plan(circ, B, tun)
     if not args.ckpt_interval:
         mb = probe.info.micro_batch
         c = autotune.optimal_ckpt(probe.info.fused_passes, B, mb, True)
         tun = qfuse.make_tuning(micro_batch=mb, fusion_depth=args.fusion_depth, ckpt_interval=c,
-                                tile_qubits=args.tile_qubits, reg_qubits=args.reg_qubits)
+                                tile_qubits=args.tile_qubits, reg_qubits=args.reg_qubits,
+                                epoch_fill=args.epoch_fill)
     del probe
     plan = qfuse.Plan(circ, B, tun)
     info = plan.info
@@ -338,7 +342,7 @@ def bench_mixed(args, dev) -> int:
     xs = [torch.tensor(c.x, device=dev) for c in ws]
     dEs = [torch.ones(s, 1, device=dev) for s in samples]
     t0 = time.perf_counter()
-    batch = qfuse.Batch(circs, samples)
+    batch = qfuse.Batch(circs, samples, qfuse.make_tuning(epoch_fill=args.epoch_fill) if args.epoch_fill else None)
     t_create = time.perf_counter() - t0
     info = batch.info
     wsb = batch.new_workspace(dev)

@@ -115,6 +115,14 @@ typedef struct {
                                all arithmetic stay float32.  Expectations are
                                unchanged; gradients carry the rounding of the stored
                                states.  Fused mode only; 0 = off                       */
+  int32_t epoch_fill;       /* planner: a register epoch at the end of a fused pass
+                               that would hold fewer than epoch_fill runs is left to
+                               the next pass (fewer, fuller epochs for more passes).
+                               0 = default: reg_qubits (every partial epoch waits)
+                               for a plan, -1 for the plans of a mixed batch (whose
+                               merged launches favour fewer passes); -1 = none
+                               waits, 1..5 = that threshold.  Results are identical
+                               up to float rounding order                              */
 } qf_tuning;
 
 /* Static description of a plan, for accounting and roofline reporting. */
@@ -124,6 +132,7 @@ typedef struct {
   int32_t segments;           /* checkpoint segments                                 */
   int32_t ckpt_interval, micro_batch, store_ckpt, fusion_depth;
   int32_t mem_save;           /* stored pass outputs in bfloat16 (qf_tuning.mem_save)  */
+  int32_t epoch_fill;         /* threshold the planner used (qf_tuning.epoch_fill)   */
   int64_t n_runs;             /* fused single-qubit runs                              */
   int64_t n_perm, n_u2, n_cz; /* ops per sample summed over forward passes            */
   double fwd_bytes_per_sample;   /* algorithmic HBM bytes, forward                    */

@@ -32,7 +32,9 @@ TUNED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_co
 # (tile qubits, register qubits) shapes with compiled kernels
 TILE_SHAPES = ((12, 4), (13, 5), (11, 4))
 FUSION_DEPTHS = (4, 6, 8, 10, 12, 16)
-MICRO_BATCHES = (8, 16, 32, 64)
+MICRO_BATCHES = (8, 16, 32, 64, 128)
+# end-of-pass epoch thresholds tried besides the default (every partial epoch waits): none waits, half
+EPOCH_FILLS = (-1, 2)
 
 
 def paper_memory_bytes(stored_per_layer: float, d: int, b: float, m_sv: int) -> float:
@@ -105,13 +107,14 @@ def cached_tuning(n_qubits, gates, n_obs, batch, device, path: str = TUNED_CACHE
 
 def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequence[int], batch: int,
              budget_bytes: Optional[int] = None, prefix_gates: int = 6000, reps: int = 2,
-             shapes=TILE_SHAPES, depths=FUSION_DEPTHS, micro_batches=MICRO_BATCHES,
+             shapes=TILE_SHAPES, depths=FUSION_DEPTHS, micro_batches=MICRO_BATCHES, epoch_fills=EPOCH_FILLS,
              cache_path: Optional[str] = None, log=None) -> dict:
     """Times the candidates on the current GPU and returns the chosen tuning fields.
 
     Each candidate (tile shape, fusion depth, micro-batch) runs forward + backward
     of one micro-batch on a prefix of the gate list; the time per sample is scaled
-    by the gate count.  The checkpoint interval then minimises the workspace of
+    by the gate count.  The best one is then timed with the other end-of-pass
+    epoch thresholds (epoch_fills).  The checkpoint interval then minimises the workspace of
     the full circuit (memory model above), keeping checkpoints for the whole batch
     when they fit the budget.
     """
@@ -129,44 +132,60 @@ def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequen
     rng = np.random.default_rng(0)
     results = []
     circ = qfuse.Circuit(n_qubits, pre, max(P_used, 1), n_inputs, z_masks)
+    def measure(k, r, F, mb, fill=0):
+        """ms per sample of the full circuit, from forward + backward of one micro-batch on the prefix."""
+        try:
+            plan = qfuse.Plan(circ, mb, qfuse.make_tuning(tile_qubits=k, reg_qubits=r, fusion_depth=F,
+                                                          micro_batch=mb, epoch_fill=fill))
+        except qfuse.QFuseError:
+            return None
+        x = torch.tensor(rng.uniform(-3.14, 3.14, size=(mb, n_inputs)).astype(np.float32), device=dev) \
+            if n_inputs else None
+        ws = plan.new_workspace(dev)
+        dE = torch.ones(mb, len(z_masks), device=dev)
+        best = float("inf")
+        for _ in range(reps + 1):
+            s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s0.record()
+            plan.forward(theta, x, ws)
+            plan.backward(theta, x, dE, ws)
+            s1.record()
+            torch.cuda.synchronize()
+            best = min(best, s0.elapsed_time(s1))
+        del ws, plan
+        per_sample_full = best / mb * (G / len(pre))
+        res = {"tile_qubits": k, "reg_qubits": r, "fusion_depth": F, "micro_batch": mb, "epoch_fill": fill,
+               "ms_per_sample": round(per_sample_full, 4)}
+        if log:
+            log(f"autotune k={k} r={r} F={F} mb={mb} fill={fill}: {per_sample_full:.3f} ms/sample")
+        return res
+
     for (k, r) in shapes:
         if k > n_qubits and (k, r) != shapes[0]:
             continue
         for F in depths:
             for mb in sorted(set(min(m, batch) for m in micro_batches)):
-                try:
-                    plan = qfuse.Plan(circ, mb, qfuse.make_tuning(tile_qubits=k, reg_qubits=r, fusion_depth=F,
-                                                                  micro_batch=mb))
-                except qfuse.QFuseError:
-                    continue
-                x = torch.tensor(rng.uniform(-3.14, 3.14, size=(mb, n_inputs)).astype(np.float32), device=dev) \
-                    if n_inputs else None
-                ws = plan.new_workspace(dev)
-                dE = torch.ones(mb, len(z_masks), device=dev)
-                best = float("inf")
-                for _ in range(reps + 1):
-                    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    s0.record()
-                    plan.forward(theta, x, ws)
-                    plan.backward(theta, x, dE, ws)
-                    s1.record()
-                    torch.cuda.synchronize()
-                    best = min(best, s0.elapsed_time(s1))
-                per_sample_full = best / mb * (G / len(pre))
-                results.append({"tile_qubits": k, "reg_qubits": r, "fusion_depth": F, "micro_batch": mb,
-                                "ms_per_sample": round(per_sample_full, 4)})
-                if log:
-                    log(f"autotune k={k} r={r} F={F} mb={mb}: {per_sample_full:.3f} ms/sample")
-                del ws, plan
+                res = measure(k, r, F, mb)
+                if res is not None:
+                    results.append(res)
+    # the end-of-pass epoch threshold, tried for the best grid point (it trades
+    # epochs against passes, which depends on the entangler pattern)
+    if results:
+        b = min(results, key=lambda d: d["ms_per_sample"])
+        for fill in epoch_fills:
+            res = measure(b["tile_qubits"], b["reg_qubits"], b["fusion_depth"], b["micro_batch"], fill)
+            if res is not None:
+                results.append(res)
     if not results:
         raise RuntimeError("no candidate tuning could be planned")
     best = min(results, key=lambda d: d["ms_per_sample"])
-    out = {k: best[k] for k in ("tile_qubits", "reg_qubits", "fusion_depth", "micro_batch")}
+    out = {k: best[k] for k in ("tile_qubits", "reg_qubits", "fusion_depth", "micro_batch", "epoch_fill")}
     # checkpoint interval from the memory model of the full circuit
     full = qfuse.Circuit(n_qubits, gates, n_params, n_inputs, z_masks)
     probe = qfuse.Plan(full, batch, qfuse.make_tuning(tile_qubits=out["tile_qubits"], reg_qubits=out["reg_qubits"],
                                                       fusion_depth=out["fusion_depth"],
-                                                      micro_batch=out["micro_batch"]))
+                                                      micro_batch=out["micro_batch"],
+                                                      epoch_fill=out["epoch_fill"]))
     passes = probe.info.fused_passes
     free = torch.cuda.mem_get_info()[0]
     budget = budget_bytes if budget_bytes is not None else int(0.85 * free)
@@ -186,7 +205,7 @@ def tuning_from(d: dict):
     return qfuse.make_tuning(tile_qubits=d.get("tile_qubits", 0), reg_qubits=d.get("reg_qubits", 0),
                              fusion_depth=d.get("fusion_depth", 0), ckpt_interval=d.get("ckpt_interval", 0),
                              micro_batch=d.get("micro_batch", 0), store_ckpt=d.get("store_ckpt", -1),
-                             mem_save=d.get("mem_save", 0))
+                             mem_save=d.get("mem_save", 0), epoch_fill=d.get("epoch_fill", 0))
 
 
 def main(argv=None) -> int:

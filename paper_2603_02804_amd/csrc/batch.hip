@@ -260,9 +260,16 @@ qf_status qf_batch_create(const qf_circuit* const* circuits, const int32_t* samp
   }
   hipGetDevice(&b->device);
   b->samples.assign(samples, samples + n_circuits);
+  // merged launches step every circuit pass by pass, so by default no
+  // end-of-pass epoch waits for the next pass (fewer passes, fewer steps)
+  qf_tuning bt;
+  std::memset(&bt, 0, sizeof(bt));
+  bt.store_ckpt = -1;
+  if (tuning) bt = *tuning;
+  if (bt.epoch_fill == 0) bt.epoch_fill = kBatchEpochFill;
   for (int i = 0; i < n_circuits; ++i) {
     qf_plan* p = nullptr;
-    const qf_status st = qf_plan_create(circuits[i], samples[i], tuning, &p);
+    const qf_status st = qf_plan_create(circuits[i], samples[i], &bt, &p);
     if (st != QF_OK) {
       const std::string m = "circuit " + std::to_string(i) + ": " + qf_last_error();
       destroy_batch(b);

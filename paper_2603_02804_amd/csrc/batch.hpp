@@ -23,6 +23,11 @@
 
 namespace qf {
 
+// Default end-of-pass epoch threshold of the plans of a mixed batch (tuning
+// epoch_fill 0): none waits, since merged launches advance every circuit one
+// pass per step and extra passes cost whole steps.
+constexpr int kBatchEpochFill = -1;
+
 // Compiled pass kernel variants: register qubits R in 1..5, NT in {64,128,256},
 // forward or backward.
 constexpr int kPassClasses = 30;

@@ -597,7 +597,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
             if (diag_layout >= 0)
               cx.diagt(a, l, ph, diag_layout, cld(&E->czg_first), cld(&E->czg_count), cld(&E->pev_first),
                        cld(&E->pev_count));
-            if (n_pha > 0) cx.phasea(a, l, ph, cld(&A.phas[pha0].regbit), cld(&A.phas[pha0].pev));
+            for (int p = pha0; p < pha0 + n_pha; ++p) cx.phasea(a, l, ph, cld(&A.phas[p].regbit), cld(&A.phas[p].pev));
             if (cza >= 0) cx.cza(a, l, ph, cza, cza_layout);
             cx.ryg(a, l, ph, ry_first, ry_mask);
           } else {
@@ -605,7 +605,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
             if (n_func > 0) cx.func(a, l, ph, n_func, cld(&E->func_first), 0);
             cx.ryg(a, l, ph, ry_first, ry_mask);
             if (cza >= 0) cx.cza(a, l, ph, cza, cza_layout);
-            if (n_pha > 0) cx.phasea(a, l, ph, cld(&A.phas[pha0].regbit), cld(&A.phas[pha0].pev));
+            for (int p = pha0; p < pha0 + n_pha; ++p) cx.phasea(a, l, ph, cld(&A.phas[p].regbit), cld(&A.phas[p].pev));
             if (diag_layout >= 0)
               cx.diagt(a, l, ph, diag_layout, cld(&E->czg_first), cld(&E->czg_count), cld(&E->pev_first),
                        cld(&E->pev_count));

@@ -399,6 +399,7 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
   S.NT = std::max(64, S.active);
   S.tiles_log2 = n - k;
   S.fusion = F;
+  S.fill = T.fill == 0 ? R : std::max(0, T.fill);
   std::vector<Unit> units_unused;
   std::vector<std::vector<int>> wire_unused;
   build_runs(C, S, &units_unused, &wire_unused, false);
@@ -664,6 +665,11 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
       for (int q : local)
         if (has_run(q) && pass_runs[q] < F && gap_released(q)) cands.push_back(q);
       if (cands.empty()) break;
+      // an epoch with fewer than S.fill runs at the end of a pass whose runs
+      // are not the circuit's last: leave them to the next pass, where they
+      // fill whole epochs (fewer epochs for more passes); a pass that has not
+      // done any work yet takes them
+      if ((int)cands.size() < S.fill && slot > 0 && runs_left > (int64_t)cands.size()) break;
       // wires whose items are all applied first (no per-amplitude work), then priority
       cands = by_priority(cands);
       std::stable_sort(cands.begin(), cands.end(), [&](int a, int b) { return gap_clear(a) > gap_clear(b); });

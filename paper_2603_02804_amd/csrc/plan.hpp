@@ -46,11 +46,13 @@ struct Tuning {
   int micro = 0;         // samples per micro-batch
   int store = -1;        // keep checkpoints of the whole batch in the forward
   int memsave = 0;       // stored pass outputs of the active segment as bfloat16 pairs
+  int fill = 0;          // end-of-pass epochs with fewer runs wait (0: R, -1: none)
 };
 
 struct Schedule {
   int n = 0, k = 0, R = 0, NT = 0, active = 0, tiles_log2 = 0, thread_bits = 0;
   int fusion = 0;
+  int fill = 0;                       // end-of-pass epochs with fewer runs wait for the next pass
   std::vector<RunRec> runs;
   std::vector<int32_t> run_gates;     // GateRec indices of each run, forward order
   std::vector<GateRec> gates;         // rotations in circuit order

@@ -135,8 +135,9 @@ struct PhaEntry {
 };
 
 // The sub-ops of one epoch; -1 / 0 fields mark sub-ops that are absent.  At
-// most kEpochMaxPhaseA PHASEA sub-ops (epochs with more stay unfused).
-constexpr int kEpochMaxPhaseA = 1;
+// most kEpochMaxPhaseA PHASEA sub-ops (epochs with more stay unfused; they are
+// diagonal, so their order within the epoch does not matter).
+constexpr int kEpochMaxPhaseA = 8;
 struct EpochRec {
   int32_t perm_from, perm_to;                          // PERM (from -1: none)
   int32_t diag_layout, czg_first, czg_count, pev_first, pev_count;   // DIAGT (layout -1: none)

@@ -727,7 +727,7 @@ int qfc_run_psi0(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tu
     Tuning T;
     if (tuning) {
       T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
-      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save;
+      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save; T.fill = tuning->epoch_fill;
     }
     if (T.mode == 2) { g_err = "the checker runs float plans only"; return QF_ERR_UNSUPPORTED; }
     PlanCore pc;
@@ -766,7 +766,7 @@ int qfc_stats(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tunin
   Tuning T;
   if (tuning) {
     T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
-    T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save;
+    T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save; T.fill = tuning->epoch_fill;
   }
   PlanCore pc;
   st = build_plan_core(C, batch, T, &pc, &msg);
@@ -792,8 +792,9 @@ int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, i
     Tuning T;
     if (tuning) {
       T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
-      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save;
+      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save; T.fill = tuning->epoch_fill;
     }
+    if (T.fill == 0) T.fill = kBatchEpochFill;
     std::vector<std::unique_ptr<PlanCore>> pcs;
     std::vector<const PlanCore*> cores;
     std::vector<PlanPtrs> ptrs;

@@ -582,12 +582,14 @@ qf_status qf_plan_create(const qf_circuit* circuit, int32_t batch, const qf_tuni
     T.micro = tuning->micro_batch;
     T.store = tuning->store_ckpt;
     T.memsave = tuning->mem_save;
+    T.fill = tuning->epoch_fill;
     if (T.mode < 0 || T.mode > 2) return fail(QF_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
     if (T.k < 0 || T.k > kMaxTileQubits) return fail(QF_ERR_INVALID_ARG, "tile_qubits out of range");
     if (T.R < 0 || T.R > kMaxR) return fail(QF_ERR_INVALID_ARG, "reg_qubits out of range");
     if (T.fusion < 0 || T.ckpt < 0 || T.micro < 0) return fail(QF_ERR_INVALID_ARG, "negative tuning value");
     if (T.memsave != 0 && T.memsave != 1) return fail(QF_ERR_INVALID_ARG, "mem_save must be 0 or 1");
     if (T.memsave && T.mode != 0) return fail(QF_ERR_INVALID_ARG, "mem_save applies to the fused mode only");
+    if (T.fill < -1 || T.fill > kMaxR) return fail(QF_ERR_INVALID_ARG, "epoch_fill must be -1..5");
   }
   qf_plan* p = nullptr;
   try {
@@ -662,6 +664,7 @@ qf_status qf_plan_get_info(const qf_plan* p, qf_plan_info* info) {
   info->store_ckpt = c.store;
   info->mem_save = c.memsave;
   info->fusion_depth = S.fusion;
+  info->epoch_fill = S.fill;
   info->n_perm = S.n_perm;
   info->n_u2 = S.n_u2;
   info->n_cz = S.n_cz;

@@ -24,6 +24,7 @@ def _dEs(ws, seed):
     dict(n=5, qubits=(11, 14), layers=(2, 5), samples=2, seed=12, tuning=dict(fusion_depth=2, ckpt_interval=2)),
     dict(n=4, qubits=(12, 13), layers=(3, 6), samples=5, seed=13, tuning=dict(micro_batch=2, ckpt_interval=3)),
     dict(n=4, qubits=(12, 14), layers=(4, 8), samples=3, seed=14, tuning=dict(ckpt_interval=2, mem_save=1)),
+    dict(n=4, qubits=(13, 15), layers=(4, 7), samples=2, seed=15, tuning=dict(epoch_fill=4)),
 ])
 def test_batch_replay_equals_single(case):
     ws = mixed(case["n"], case["qubits"], case["layers"], case["samples"], case["seed"])
@@ -33,7 +34,9 @@ def test_batch_replay_equals_single(case):
     Es, dth, dxs, st = plancheck.batch_run(circuits, samples, [c.theta for c in ws], [c.x for c in ws], dEs,
                                            **case["tuning"])
     for i, c in enumerate(ws):
-        E1, dth1, dx1 = plancheck.run(c.n_qubits, c.gates, c.theta, c.x, zm, dEs[i], **case["tuning"])
+        single = dict(case["tuning"])
+        single.setdefault("epoch_fill", -1)   # the default of a batch's plans
+        E1, dth1, dx1 = plancheck.run(c.n_qubits, c.gates, c.theta, c.x, zm, dEs[i], **single)
         np.testing.assert_array_equal(Es[i], E1)
         np.testing.assert_array_equal(dth[i], dth1)
         np.testing.assert_array_equal(dxs[i], dx1)

@@ -29,7 +29,7 @@ def _setup(ws, dev, seed=0):
 def _single(circs, ws, thetas, xs, dEs, dev):
     out = []
     for c, w, t, x, d in zip(circs, ws, thetas, xs, dEs):
-        plan = qfuse.Plan(c, w.x.shape[0])
+        plan = qfuse.Plan(c, w.x.shape[0], qfuse.make_tuning(epoch_fill=-1))   # a batch's default
         wsb = plan.new_workspace(dev)
         E = plan.forward(t, x, wsb)
         dth, dx = plan.backward(t, x, d, wsb)

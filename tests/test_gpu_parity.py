@@ -97,6 +97,7 @@ def test_single_tile(orc, n, L, rots, B, tun):
     (14, 3, ("RX", "RY", "RZ"), 3, {}),
     (15, 4, ("RY", "RZ"), 2, {"store_ckpt": 0, "micro_batch": 1}),
     (16, 3, ("RX", "RY", "RZ"), 2, {"fusion_depth": 8}),
+    (14, 6, ("RY", "RZ"), 2, {"fusion_depth": 12}),   # epochs with up to 3 register-bit phases
 ])
 def test_multi_tile(orc, n, L, rots, B, tun):
     gates, theta, x = hea_case(n, L, rots, B)
@@ -125,6 +126,14 @@ def test_general_gate_list(orc):
     theta, x, _ = draw_inputs(9, 40, B, n)
     compare(orc, n, gates, theta, x, [0, 5, 10])
     compare(orc, n, gates, theta, x, [0, 5, 10], tile_qubits=8, reg_qubits=3, fusion_depth=2)
+
+
+@pytest.mark.parametrize("fill", [-1, 1, 2, 0])
+def test_epoch_fill(orc, fill):
+    """Each end-of-pass epoch threshold (a ring: partial epochs at pass ends are common)."""
+    gates = hea_gates(14, 5, ("RX", "RY", "RZ"), ring=True)
+    theta, x, _ = draw_inputs(31, 5 * 3 * 14, 2, 14)
+    compare(orc, 14, gates, theta, x, [0, 7, 13], epoch_fill=fill)
 
 
 def test_ring_and_z_strings(orc):

@@ -28,6 +28,7 @@ MULTI = [
     (14, 3, ("RX", "RY", "RZ"), 3, {}),
     (15, 4, ("RY", "RZ"), 2, {"store_ckpt": 0, "micro_batch": 1}),
     (16, 3, ("RX", "RY", "RZ"), 2, {"fusion_depth": 8}),
+    (14, 6, ("RY", "RZ"), 2, {"fusion_depth": 12}),   # epochs with up to 3 register-bit phases
 ]
 
 
@@ -104,3 +105,27 @@ def test_schedule_shape_at_benchmark_sizes():
     assert st["runs"] == 20 * 1000          # encoding merged into layer 1
     assert st["u2"] == st["runs"]           # every run applied exactly once
     assert st["passes"] < 1000              # more than one layer per pass on average
+
+
+@pytest.mark.parametrize("fill", [-1, 1, 2, 0])
+def test_epoch_fill_programs(orc, fill):
+    """Every end-of-pass epoch threshold gives the same results (a ring, so that
+    partial epochs at pass ends are common)."""
+    gates = hea_gates(14, 5, ("RX", "RY", "RZ"), ring=True)
+    theta, x, _ = draw_inputs(31, 5 * 3 * 14, 2, 14)
+    check(orc, 14, gates, theta, x, [0, 7, 13], epoch_fill=fill)
+
+
+def test_epoch_fill_trades_epochs_for_passes():
+    """Leaving partial end-of-pass epochs to the next pass: no more register
+    epochs (PERMs), and on a CZ ring far fewer, for at most a few more passes."""
+    g = hea_gates(20, 60, ("RX", "RY", "RZ"), encoding=False, ring=True)
+    off = pc.stats(20, g, 3600, 0, [1], 8, epoch_fill=-1)
+    on = pc.stats(20, g, 3600, 0, [1], 8)
+    assert on["u2"] == off["u2"] == 20 * 60
+    assert on["perm"] < 0.95 * off["perm"]
+    assert on["passes"] < off["passes"]
+    g = hea_gates(20, 60, ("RX", "RY", "RZ"))
+    off = pc.stats(20, g, 3600, 20, [1], 8, epoch_fill=-1)
+    on = pc.stats(20, g, 3600, 20, [1], 8)
+    assert on["perm"] <= off["perm"] and on["passes"] <= off["passes"] + 2
