@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--micro-batch", type=int, default=0)
     ap.add_argument("--tile-qubits", type=int, default=0)
     ap.add_argument("--reg-qubits", type=int, default=0)
+    ap.add_argument("--uncompute", type=int, choices=(0, 1), default=None,
+                    help="1: adjoint passes rebuild psi (no recompute); 0: recompute segments (default: autotuned, "
+                         "else 1)")
     ap.add_argument("--epoch-fill", type=int, default=0,
                     help="end-of-pass epochs with fewer runs wait for the next pass (0: register qubits, -1: none)")
     ap.add_argument("--no-baselines", action="store_true", help="skip the per-gate and CPU baselines")
@@ -109,11 +112,12 @@ def main() -> int:
     x_np = w.x[:B]
     lab_np = w.labels[:B]
 
+    unc = 1 if args.uncompute is None else args.uncompute
     tun = qfuse.make_tuning(fusion_depth=args.fusion_depth, ckpt_interval=args.ckpt_interval,
                             micro_batch=args.micro_batch, tile_qubits=args.tile_qubits,
-                            reg_qubits=args.reg_qubits, epoch_fill=args.epoch_fill)
+                            reg_qubits=args.reg_qubits, epoch_fill=args.epoch_fill, uncompute=unc)
     tuning_src = "flags" if any((args.fusion_depth, args.ckpt_interval, args.micro_batch, args.tile_qubits,
-                                 args.reg_qubits, args.epoch_fill)) else "default"
+                                 args.reg_qubits, args.epoch_fill, args.uncompute is not None)) else "default"
     if tuning_src == "default" and not args.no_autotune:
         from paper_2603_02804_amd import autotune
         cached = autotune.cached_tuning(w.n_qubits, w.gates, w.n_obs, B, autotune.device_key(dev))
@@ -162,7 +166,8 @@ def main() -> int:
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         # per-sample bytes depend on the pass structure, not on how samples are grouped into micro-batches
-        shape = {k: getattr(info, k) for k in ("tile_qubits", "reg_qubits", "fusion_depth", "fused_passes")}
+        shape = {k: getattr(info, k) for k in ("tile_qubits", "reg_qubits", "fusion_depth", "fused_passes",
+                                               "uncompute")}
         if tr.get("kernel_src_sha") == kernel_sha() and tr.get("plan") == shape and not args.layers:
             # counters were taken per sample over every adjoint pass launch
             traffic = round(tr["hbm_bytes_per_sample"] * B * args.steps / max(1, n_bwd))
@@ -191,7 +196,7 @@ def main() -> int:
                    "batch": B, "micro_batch": info.micro_batch, "tile_qubits": info.tile_qubits,
                    "reg_qubits": info.reg_qubits, "fusion_depth": info.fusion_depth, "fused_passes": info.fused_passes,
                    "ckpt_interval": info.ckpt_interval, "segments": info.segments, "epoch_fill": info.epoch_fill,
-                   "tuning": tuning_src},
+                   "uncompute": info.uncompute, "tuning": tuning_src},
         "roofline": roofline,
         "hbm": {"gbs": round(hbm_gbs, 1), "frac": round(hbm_gbs / PEAK_HBM_GBS, 4),
                 "bytes_per_sample": info.fwd_bytes_per_sample + info.bwd_bytes_per_sample},
@@ -279,16 +284,21 @@ def bench_paper(args, dev) -> int:
     psi0 /= torch.linalg.vector_norm(psi0, dim=1, keepdim=True)
     xm, zm = pauli_string(("IXYZ" * 5)[:n])
     circ = qfuse.Circuit(n, gates, L * 3 * n, 0, [zm], [xm])
+    unc = 1 if args.uncompute is None else args.uncompute
     tun = qfuse.make_tuning(micro_batch=args.micro_batch or 128, fusion_depth=args.fusion_depth,
                             ckpt_interval=args.ckpt_interval, tile_qubits=args.tile_qubits,
-                            reg_qubits=args.reg_qubits, epoch_fill=args.epoch_fill)
+                            reg_qubits=args.reg_qubits, epoch_fill=args.epoch_fill, uncompute=unc)
     probe = qfuse.Plan(circ, B, tun)
     if not args.ckpt_interval:
         mb = probe.info.micro_batch
-        c = autotune.optimal_ckpt(probe.info.fused_passes, B, mb, True)
+        if unc:
+            store, c = autotune.uncompute_storage(probe.info.fused_passes, B, mb, 8 << n,
+                                                  0.85 * torch.cuda.mem_get_info()[0])
+        else:
+            store, c = 1, autotune.optimal_ckpt(probe.info.fused_passes, B, mb, True)
         tun = qfuse.make_tuning(micro_batch=mb, fusion_depth=args.fusion_depth, ckpt_interval=c,
                                 tile_qubits=args.tile_qubits, reg_qubits=args.reg_qubits,
-                                epoch_fill=args.epoch_fill)
+                                epoch_fill=args.epoch_fill, uncompute=unc, store_ckpt=store)
     del probe
     plan = qfuse.Plan(circ, B, tun)
     info = plan.info
@@ -317,7 +327,7 @@ def bench_paper(args, dev) -> int:
         "config": {"workload": f"paper20q{L}l: 20-qubit HEA, {L} layers of RX,RY,RZ + CZ ring, random initial "
                                "states, O = (IXYZ)^5, L = sum E",
                    "batch": B, "micro_batch": info.micro_batch, "fused_passes": info.fused_passes,
-                   "ckpt_interval": info.ckpt_interval, "segments": info.segments,
+                   "ckpt_interval": info.ckpt_interval, "segments": info.segments, "uncompute": info.uncompute,
                    "paper": "1,273 s per 1,000-sample epoch on GH200 (Table 1): 0.786 samples/s; context, "
                             "other hardware"},
     }

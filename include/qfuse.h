@@ -123,6 +123,15 @@ typedef struct {
                                merged launches favour fewer passes); -1 = none
                                waits, 1..5 = that threshold.  Results are identical
                                up to float rounding order                              */
+  int32_t uncompute;        /* backward state reconstruction: 0 = the paper's scheme
+                               (each checkpoint segment is recomputed forward and its
+                               pass outputs stored, Sec. 3.3-3.4); 1 = every fused
+                               adjoint pass also writes psi at its input, un-applied
+                               in registers as the pass already does for its gates
+                               (reversibility, Sec. 3.3), so the backward recomputes
+                               and stores nothing; each segment starts again from its
+                               exact checkpoint, so float32 drift spans one segment.
+                               Fused mode only, not with mem_save                      */
 } qf_tuning;
 
 /* Static description of a plan, for accounting and roofline reporting. */
@@ -133,6 +142,7 @@ typedef struct {
   int32_t ckpt_interval, micro_batch, store_ckpt, fusion_depth;
   int32_t mem_save;           /* stored pass outputs in bfloat16 (qf_tuning.mem_save)  */
   int32_t epoch_fill;         /* threshold the planner used (qf_tuning.epoch_fill)   */
+  int32_t uncompute;          /* qf_tuning.uncompute                                 */
   int64_t n_runs;             /* fused single-qubit runs                              */
   int64_t n_perm, n_u2, n_cz; /* ops per sample summed over forward passes            */
   double fwd_bytes_per_sample;   /* algorithmic HBM bytes, forward                    */

@@ -47,15 +47,21 @@ def paper_optimal_block(stored_per_layer: float, d: int) -> float:
 
 
 def plan_states(passes: int, ckpt: int, batch: int, micro_batch: int, store: bool = True,
-                mem_save: bool = False) -> float:
+                mem_save: bool = False, uncompute: bool = False) -> float:
     """States held by a plan's workspace: checkpoints + one segment of pass outputs + ping-pong buffers.
 
     In the memory-saving mode the segment's pass outputs are bfloat16 pairs, half a state each (Sec. 3.4:
-    the stored-output coefficient of the memory model is halved)."""
+    the stored-output coefficient of the memory model is halved).  In the uncompute mode the adjoint
+    passes rebuild psi, so no pass outputs are stored."""
     segs = -(-passes // ckpt)
     kept = batch if store else micro_batch
-    seg_states = max(0, ckpt - 1) * micro_batch
+    seg_states = 0 if uncompute else max(0, ckpt - 1) * micro_batch
     return segs * kept + (seg_states / 2 if mem_save else seg_states) + 4 * micro_batch
+
+
+# Longest checkpoint segment of the uncompute mode: psi is rebuilt in float32
+# through at most this many fused passes before it restarts from a checkpoint.
+UNCOMPUTE_MAX_SEGMENT = 64
 
 
 def optimal_ckpt(passes: int, batch: int, micro_batch: int, store: bool = True, mem_save: bool = False) -> int:
@@ -65,6 +71,19 @@ def optimal_ckpt(passes: int, batch: int, micro_batch: int, store: bool = True, 
     best = min(range(max(1, guess // 2), min(passes, 2 * guess) + 1),
                key=lambda c: (plan_states(passes, c, batch, micro_batch, store, mem_save), c))
     return best
+
+
+def uncompute_storage(passes: int, batch: int, micro_batch: int, state_bytes: int, budget: float):
+    """(store_ckpt, ckpt_interval) of the uncompute mode: checkpoints for the whole batch every
+    UNCOMPUTE_MAX_SEGMENT passes, or fewer segments until they fit, else checkpoints per micro-batch."""
+    c = min(passes, UNCOMPUTE_MAX_SEGMENT)
+    for store in (1, 0):
+        for ck in range(c, passes + 1):
+            if plan_states(passes, ck, batch, micro_batch, bool(store), False, True) * state_bytes <= budget:
+                return store, ck
+            if -(-passes // ck) == 1:
+                break
+    return 0, c
 
 
 def choose_storage(passes: int, batch: int, micro_batch: int, state_bytes: int, budget: float):
@@ -112,9 +131,11 @@ def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequen
     """Times the candidates on the current GPU and returns the chosen tuning fields.
 
     Each candidate (tile shape, fusion depth, micro-batch) runs forward + backward
-    of one micro-batch on a prefix of the gate list; the time per sample is scaled
-    by the gate count.  The best one is then timed with the other end-of-pass
-    epoch thresholds (epoch_fills).  The checkpoint interval then minimises the workspace of
+    of one micro-batch on a prefix of the gate list, with the adjoint passes
+    rebuilding psi (uncompute); the time per sample is scaled by the gate count.
+    The best one is then timed with the other end-of-pass epoch thresholds
+    (epoch_fills), and the best of those with the recompute scheme.  For the
+    recompute scheme the checkpoint interval then minimises the workspace of
     the full circuit (memory model above), keeping checkpoints for the whole batch
     when they fit the budget.
     """
@@ -132,11 +153,11 @@ def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequen
     rng = np.random.default_rng(0)
     results = []
     circ = qfuse.Circuit(n_qubits, pre, max(P_used, 1), n_inputs, z_masks)
-    def measure(k, r, F, mb, fill=0):
+    def measure(k, r, F, mb, fill=0, unc=1):
         """ms per sample of the full circuit, from forward + backward of one micro-batch on the prefix."""
         try:
             plan = qfuse.Plan(circ, mb, qfuse.make_tuning(tile_qubits=k, reg_qubits=r, fusion_depth=F,
-                                                          micro_batch=mb, epoch_fill=fill))
+                                                          micro_batch=mb, epoch_fill=fill, uncompute=unc))
         except qfuse.QFuseError:
             return None
         x = torch.tensor(rng.uniform(-3.14, 3.14, size=(mb, n_inputs)).astype(np.float32), device=dev) \
@@ -155,9 +176,9 @@ def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequen
         del ws, plan
         per_sample_full = best / mb * (G / len(pre))
         res = {"tile_qubits": k, "reg_qubits": r, "fusion_depth": F, "micro_batch": mb, "epoch_fill": fill,
-               "ms_per_sample": round(per_sample_full, 4)}
+               "uncompute": unc, "ms_per_sample": round(per_sample_full, 4)}
         if log:
-            log(f"autotune k={k} r={r} F={F} mb={mb} fill={fill}: {per_sample_full:.3f} ms/sample")
+            log(f"autotune k={k} r={r} F={F} mb={mb} fill={fill} uncompute={unc}: {per_sample_full:.3f} ms/sample")
         return res
 
     for (k, r) in shapes:
@@ -169,17 +190,23 @@ def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequen
                 if res is not None:
                     results.append(res)
     # the end-of-pass epoch threshold, tried for the best grid point (it trades
-    # epochs against passes, which depends on the entangler pattern)
+    # epochs against passes, which depends on the entangler pattern); then the
+    # recompute scheme for the best of those
     if results:
         b = min(results, key=lambda d: d["ms_per_sample"])
         for fill in epoch_fills:
             res = measure(b["tile_qubits"], b["reg_qubits"], b["fusion_depth"], b["micro_batch"], fill)
             if res is not None:
                 results.append(res)
+        b = min(results, key=lambda d: d["ms_per_sample"])
+        res = measure(b["tile_qubits"], b["reg_qubits"], b["fusion_depth"], b["micro_batch"], b["epoch_fill"], 0)
+        if res is not None:
+            results.append(res)
     if not results:
         raise RuntimeError("no candidate tuning could be planned")
     best = min(results, key=lambda d: d["ms_per_sample"])
-    out = {k: best[k] for k in ("tile_qubits", "reg_qubits", "fusion_depth", "micro_batch", "epoch_fill")}
+    out = {k: best[k] for k in ("tile_qubits", "reg_qubits", "fusion_depth", "micro_batch", "epoch_fill",
+                                "uncompute")}
     # checkpoint interval from the memory model of the full circuit
     full = qfuse.Circuit(n_qubits, gates, n_params, n_inputs, z_masks)
     probe = qfuse.Plan(full, batch, qfuse.make_tuning(tile_qubits=out["tile_qubits"], reg_qubits=out["reg_qubits"],
@@ -189,7 +216,11 @@ def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequen
     passes = probe.info.fused_passes
     free = torch.cuda.mem_get_info()[0]
     budget = budget_bytes if budget_bytes is not None else int(0.85 * free)
-    store, mem_save, c = choose_storage(passes, batch, out["micro_batch"], 8 << n_qubits, budget)
+    if out["uncompute"]:
+        store, c = uncompute_storage(passes, batch, out["micro_batch"], 8 << n_qubits, budget)
+        mem_save = 0
+    else:
+        store, mem_save, c = choose_storage(passes, batch, out["micro_batch"], 8 << n_qubits, budget)
     out.update({"ckpt_interval": c, "store_ckpt": store, "mem_save": mem_save, "candidates": results, "device": name,
                 "passes": passes, "prefix_gates": len(pre)})
     if cache_path:
@@ -205,7 +236,8 @@ def tuning_from(d: dict):
     return qfuse.make_tuning(tile_qubits=d.get("tile_qubits", 0), reg_qubits=d.get("reg_qubits", 0),
                              fusion_depth=d.get("fusion_depth", 0), ckpt_interval=d.get("ckpt_interval", 0),
                              micro_batch=d.get("micro_batch", 0), store_ckpt=d.get("store_ckpt", -1),
-                             mem_save=d.get("mem_save", 0), epoch_fill=d.get("epoch_fill", 0))
+                             mem_save=d.get("mem_save", 0), epoch_fill=d.get("epoch_fill", 0),
+                             uncompute=d.get("uncompute", 0))
 
 
 def main(argv=None) -> int:

@@ -56,6 +56,7 @@ __global__ __launch_bounds__(NT, (pass_min_waves<R, BWD>())) void k_pass_multi(c
   A.src1 = rebase(A.src1, ws);
   A.dst = rebase(A.dst, ws);
   A.dst2 = rebase(A.dst2, ws);
+  A.dpsi = rebase(A.dpsi, ws);
   A.partF = rebase(A.partF, ws);
   A.partE = rebase(A.partE, ws);
   A.dE = cld(&ptrs[circ].dE);

@@ -260,6 +260,7 @@ inline bool check_pass_job(const PassJob& j, const PlanCore& c, uint32_t blocks,
   ok &= in_region(A.src1, state_ext(A.s1, 0), r);
   ok &= in_region(A.dst, state_ext(A.sd, 0), r);
   ok &= in_region(A.dst2, state_ext(A.sd2, 1), r);
+  ok &= in_region(A.dpsi, state_ext(A.sdp, 0), r);
   ok &= in_region(A.partF, nb * c.tiles * 3 * ns * 4, r);
   ok &= in_region(A.partE, nb * c.tiles * (uint64_t)c.waves * c.C.K * 4, r);
   ok &= in_region(A.coef_sh, 32ull * std::max(1, S.n_coef_shared), r);

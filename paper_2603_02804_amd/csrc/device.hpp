@@ -549,8 +549,19 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         if (active && A.dst) {
           float2* dst = reinterpret_cast<float2*>(A.dst) + (long long)sl * A.sd;
           if constexpr (BWD) {
+            if (A.dpsi) {
+              // also psi, un-applied to the pass input, in the same memory order
+              float2* dp = reinterpret_cast<float2*>(A.dpsi) + (long long)sl * A.sdp;
 #pragma unroll
-            for (int jj = 0; jj < NA; ++jj) dst[base | rb(jj)] = l[jj];
+              for (int jj = 0; jj < NA; ++jj) {
+                const uint32_t i = base | rb(jj);
+                dst[i] = l[jj];
+                dp[i] = a[jj];
+              }
+            } else {
+#pragma unroll
+              for (int jj = 0; jj < NA; ++jj) dst[base | rb(jj)] = l[jj];
+            }
           } else {
 #pragma unroll
             for (int jj = 0; jj < NA; ++jj) dst[base | rb(jj)] = a[jj];

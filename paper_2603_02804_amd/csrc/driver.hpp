@@ -35,6 +35,7 @@ struct PassLaunch {
   // 1 per bfloat16 pair)
   bool src0_bf16 = false;   // psi input stored as bfloat16 pairs
   uint32_t* dst2 = nullptr; int64_t dst2_stride = 0;      // forward: bfloat16 copy of the output
+  float* dpsi = nullptr; int64_t dpsi_stride = 0;         // backward: psi at the pass input (uncompute)
   float* partF = nullptr;   // backward functional partial sums of this pass: [sample][tile][slot][3]
   float* partE = nullptr;   // forward expectation partial sums
   const float* dE = nullptr;
@@ -51,6 +52,7 @@ struct PlanCore {
   bool c128 = false;                  // complex128 validation path (double throughout)
   int P = 0, ckpt = 1, n_seg = 1, mb = 1, store = 1;
   int memsave = 0;                    // stored pass outputs of the active segment in bfloat16
+  int uncompute = 0;                  // adjoint passes write psi at their input: no recompute
   int waves = 1, tiles = 1;
   int64_t amps = 1;                   // 2^n
   size_t state_bytes = 8;
@@ -165,6 +167,7 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
   }
   c.store = T.store >= 0 ? (T.store ? 1 : 0) : 1;
   c.memsave = T.memsave ? 1 : 0;
+  c.uncompute = T.uncompute > 0 ? 1 : 0;
   // partial-sum offsets per pass, relative to the segment start
   c.partF_off.assign(c.P, 0);
   for (int s = 0; s < c.n_seg; ++s) {
@@ -196,7 +199,8 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
   c.off_ev_ps = off;   off = align_up(off + sizeof(float) * 2 * std::max<int64_t>(1, int64_t(B) * S.n_ev_ps));
   c.off_ckpt = off;    off = align_up(off + SB * size_t(nck) * c.n_seg);
   c.off_work = off;    off = align_up(off + SB * size_t(c.mb) * 2);
-  c.off_seg = off;     off = align_up(off + (c.memsave ? SB / 2 : SB) * size_t(c.mb) * std::max(0, c.ckpt - 1));
+  c.off_seg = off;     off = align_up(off + (c.uncompute ? 0 : (c.memsave ? SB / 2 : SB) * size_t(c.mb) *
+                                                               std::max(0, c.ckpt - 1)));
   c.off_lam = off;     off = align_up(off + SB * size_t(c.mb) * 2);
   c.off_partE = off;   off = align_up(off + sizeof(float) * std::max<int64_t>(1, int64_t(c.mb) * C.K *
                                                                              (S.general_obs ? c.pauli_blocks : c.tiles * c.waves)));
@@ -375,6 +379,30 @@ qf_status run_backward_fused(const PlanCore& c, Exec& ex, const float* theta, co
     int li = 0;
     for (int s = c.n_seg - 1; s >= 0; --s) {
       const int a = c.seg_begin[s], b = c.seg_begin[s + 1];
+      if (c.uncompute) {
+        // the adjoint passes rebuild psi from the segment's checkpointed output
+        // (ping-pong through the work states); nothing is recomputed or stored
+        for (int p = b - 1; p >= a; --p) {
+          PassLaunch L;
+          L.pass = p;
+          L.bwd = true;
+          L.nb = nb;
+          L.sample0 = mb0;
+          if (p == b - 1) { L.src0 = ck + s * SA; L.src0_stride = ck_stride; }
+          else { L.src0 = work + (p & 1) * SA * nb; L.src0_stride = SA; }
+          if (p == c.P - 1 && c.S.general_obs)
+            ex.pauli_seed((const float*)(ck + s * SA), ck_stride, lam + li * SA * nb, SA, nb, mb0, dE);
+          if (p != c.P - 1 || c.S.general_obs) { L.src1 = lam + li * SA * nb; L.src1_stride = SA; }
+          if (p > 0) { L.dst = lam + (1 - li) * SA * nb; L.dst_stride = SA; }
+          if (p > a) { L.dpsi = work + ((p - 1) & 1) * SA * nb; L.dpsi_stride = SA; }
+          L.partF = partF + int64_t(nb) * c.partF_off[p];
+          L.dE = dE;
+          ex.pass(L);
+          li = 1 - li;
+        }
+        ex.assemble(s, nb, mb0, theta, x, partF, Gr);
+        continue;
+      }
       // recompute the segment, storing every pass output but the last
       for (int p = a; p <= b - 2; ++p) {
         PassLaunch L;

@@ -83,6 +83,8 @@ struct KArgs {
   uint32_t* dst2;             // forward: bfloat16-pair copy of the output (memory-saving mode)
   long long sd2;              // its per-sample stride (words)
   int src0_bf16;              // psi input as bfloat16 pairs (4 bytes per amplitude)
+  float* dpsi;                // backward: psi at the pass input (uncompute mode), or null
+  long long sdp;              // its per-sample stride (complex elements)
 };
 
 // Workspace addresses of the coefficient tables of one call.
@@ -132,6 +134,8 @@ inline KArgs make_pass_args(const PlanCore& c, const PlanPtrs& d, const CoefPtrs
   A.sd = L.dst_stride / 2;
   A.dst2 = L.dst2;
   A.sd2 = L.dst2_stride;
+  A.dpsi = L.dpsi;
+  A.sdp = L.dpsi_stride / 2;
   A.partF = L.partF;
   A.partE = L.partE;
   A.dE = L.dE;

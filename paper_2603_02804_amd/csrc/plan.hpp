@@ -46,6 +46,7 @@ struct Tuning {
   int micro = 0;         // samples per micro-batch
   int store = -1;        // keep checkpoints of the whole batch in the forward
   int memsave = 0;       // stored pass outputs of the active segment as bfloat16 pairs
+  int uncompute = 0;     // the adjoint passes rebuild psi; no recompute (1: on)
   int fill = 0;          // end-of-pass epochs with fewer runs wait (0: R, -1: none)
 };
 

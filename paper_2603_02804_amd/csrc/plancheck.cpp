@@ -302,6 +302,12 @@ struct CpuExec {
                   in_ws(p, 8, "store address");
                   p[0] = v[t * NA + jj].re;
                   p[1] = v[t * NA + jj].im;
+                  if (L.bwd && L.dpsi) {   // psi at the pass input (uncompute mode)
+                    float* q = L.dpsi + sl * L.dpsi_stride + 2 * idx;
+                    in_ws(q, 8, "store address");
+                    q[0] = a[t * NA + jj].re;
+                    q[1] = a[t * NA + jj].im;
+                  }
                 }
               break;
             }
@@ -727,7 +733,7 @@ int qfc_run_psi0(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tu
     Tuning T;
     if (tuning) {
       T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
-      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save; T.fill = tuning->epoch_fill;
+      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save; T.fill = tuning->epoch_fill; T.uncompute = tuning->uncompute;
     }
     if (T.mode == 2) { g_err = "the checker runs float plans only"; return QF_ERR_UNSUPPORTED; }
     PlanCore pc;
@@ -766,7 +772,7 @@ int qfc_stats(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tunin
   Tuning T;
   if (tuning) {
     T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
-    T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save; T.fill = tuning->epoch_fill;
+    T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save; T.fill = tuning->epoch_fill; T.uncompute = tuning->uncompute;
   }
   PlanCore pc;
   st = build_plan_core(C, batch, T, &pc, &msg);
@@ -792,7 +798,7 @@ int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, i
     Tuning T;
     if (tuning) {
       T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
-      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save; T.fill = tuning->epoch_fill;
+      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save; T.fill = tuning->epoch_fill; T.uncompute = tuning->uncompute;
     }
     if (T.fill == 0) T.fill = kBatchEpochFill;
     std::vector<std::unique_ptr<PlanCore>> pcs;
@@ -849,6 +855,7 @@ int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, i
             pl.src1 = rb(pl.src1);
             pl.dst = rb(pl.dst);
             pl.dst2 = rb(pl.dst2);
+            pl.dpsi = rb(pl.dpsi);
             pl.partF = rb(pl.partF);
             pl.partE = rb(pl.partE);
             pl.dE = dE ? dE[j.circ] : nullptr;

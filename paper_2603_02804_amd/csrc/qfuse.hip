@@ -583,6 +583,7 @@ qf_status qf_plan_create(const qf_circuit* circuit, int32_t batch, const qf_tuni
     T.store = tuning->store_ckpt;
     T.memsave = tuning->mem_save;
     T.fill = tuning->epoch_fill;
+    T.uncompute = tuning->uncompute;
     if (T.mode < 0 || T.mode > 2) return fail(QF_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
     if (T.k < 0 || T.k > kMaxTileQubits) return fail(QF_ERR_INVALID_ARG, "tile_qubits out of range");
     if (T.R < 0 || T.R > kMaxR) return fail(QF_ERR_INVALID_ARG, "reg_qubits out of range");
@@ -590,6 +591,10 @@ qf_status qf_plan_create(const qf_circuit* circuit, int32_t batch, const qf_tuni
     if (T.memsave != 0 && T.memsave != 1) return fail(QF_ERR_INVALID_ARG, "mem_save must be 0 or 1");
     if (T.memsave && T.mode != 0) return fail(QF_ERR_INVALID_ARG, "mem_save applies to the fused mode only");
     if (T.fill < -1 || T.fill > kMaxR) return fail(QF_ERR_INVALID_ARG, "epoch_fill must be -1..5");
+    if (T.uncompute != 0 && T.uncompute != 1) return fail(QF_ERR_INVALID_ARG, "uncompute must be 0 or 1");
+    if (T.uncompute && T.mode != 0) return fail(QF_ERR_INVALID_ARG, "uncompute applies to the fused mode only");
+    if (T.uncompute && T.memsave)
+      return fail(QF_ERR_INVALID_ARG, "uncompute stores no pass outputs, so mem_save does not apply");
   }
   qf_plan* p = nullptr;
   try {
@@ -665,6 +670,7 @@ qf_status qf_plan_get_info(const qf_plan* p, qf_plan_info* info) {
   info->mem_save = c.memsave;
   info->fusion_depth = S.fusion;
   info->epoch_fill = S.fill;
+  info->uncompute = c.uncompute;
   info->n_perm = S.n_perm;
   info->n_u2 = S.n_u2;
   info->n_cz = S.n_cz;
@@ -679,9 +685,12 @@ qf_status qf_plan_get_info(const qf_plan* p, qf_plan_info* info) {
   double recompute = 0, adj = 0;
   for (int s = 0; s < c.n_seg; ++s) {
     const int a = c.seg_begin[s], b = c.seg_begin[s + 1];
-    for (int q = a; q <= b - 2; ++q) recompute += (q == 0 ? 0 : SB) + SB + (c.memsave ? ST : 0);
-    for (int q = a; q < b; ++q)   // psi_out, lambda_out (none for the seed pass), lambda_in (none for pass 0)
-      adj += (q == b - 1 ? SB : ST) + (q == c.P - 1 ? 0 : SB) + (q == 0 ? 0 : SB);
+    if (!c.uncompute)
+      for (int q = a; q <= b - 2; ++q) recompute += (q == 0 ? 0 : SB) + SB + (c.memsave ? ST : 0);
+    for (int q = a; q < b; ++q)   // psi_out, lambda_out (none for the seed pass), lambda_in (none for pass 0),
+                                  // psi_in in the uncompute mode (none for a segment's first pass)
+      adj += (q == b - 1 ? SB : ST) + (q == c.P - 1 ? 0 : SB) + (q == 0 ? 0 : SB) +
+             (c.uncompute && q > a ? SB : 0);
   }
   info->bwd_pass_bytes_per_sample = adj;
   info->bwd_bytes_per_sample = recompute + adj + (c.store ? 0 : info->fwd_bytes_per_sample);
@@ -695,7 +704,7 @@ qf_status qf_plan_get_info(const qf_plan* p, qf_plan_info* info) {
   const double runs = (double)S.n_u2;
   info->fwd_flops_per_sample = runs * 16 * A;
   double rec_runs = 0;
-  for (int s = 0; s < c.n_seg; ++s)
+  for (int s = 0; s < c.n_seg && !c.uncompute; ++s)
     for (int q = c.seg_begin[s]; q <= c.seg_begin[s + 1] - 2; ++q) {
       const PassRec& pr = S.passes[q];
       rec_runs += pr.n_slots;

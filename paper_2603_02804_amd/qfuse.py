@@ -48,13 +48,14 @@ class qf_circuit_desc(ctypes.Structure):
 class qf_tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("mode", "tile_qubits", "reg_qubits", "fusion_depth",
                                               "ckpt_interval", "micro_batch", "store_ckpt", "mem_save",
-                                              "epoch_fill")]
+                                              "epoch_fill", "uncompute")]
 
 
 class qf_plan_info(ctypes.Structure):
     _fields_ = ([(n, ctypes.c_int32) for n in ("n_qubits", "tile_qubits", "reg_qubits", "threads", "tiles",
                                                "fused_passes", "segments", "ckpt_interval", "micro_batch",
-                                               "store_ckpt", "fusion_depth", "mem_save", "epoch_fill")]
+                                               "store_ckpt", "fusion_depth", "mem_save", "epoch_fill",
+                                               "uncompute")]
                 + [("n_runs", ctypes.c_int64), ("n_perm", ctypes.c_int64), ("n_u2", ctypes.c_int64),
                    ("n_cz", ctypes.c_int64)]
                 + [(n, ctypes.c_double) for n in ("fwd_bytes_per_sample", "bwd_bytes_per_sample",
@@ -209,9 +210,9 @@ def qf_status_string(status: int) -> str:
 
 # --------------------------------------------------------------------- conveniences
 def make_tuning(mode=0, tile_qubits=0, reg_qubits=0, fusion_depth=0, ckpt_interval=0, micro_batch=0,
-                store_ckpt=-1, mem_save=0, epoch_fill=0) -> qf_tuning:
+                store_ckpt=-1, mem_save=0, epoch_fill=0, uncompute=0) -> qf_tuning:
     return qf_tuning(mode, tile_qubits, reg_qubits, fusion_depth, ckpt_interval, micro_batch, store_ckpt, mem_save,
-                     epoch_fill)
+                     epoch_fill, uncompute)
 
 
 class Circuit:

@@ -26,11 +26,11 @@ class Desc(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("mode", "tile_qubits", "reg_qubits", "fusion_depth",
                                               "ckpt_interval", "micro_batch", "store_ckpt", "mem_save",
-                                              "epoch_fill")]
+                                              "epoch_fill", "uncompute")]
 
 
 def make_tuning(**kw):
-    t = Tuning(0, 0, 0, 0, 0, 0, -1, 0, 0)
+    t = Tuning(0, 0, 0, 0, 0, 0, -1, 0, 0, 0)
     for k, v in kw.items():
         setattr(t, k, v)
     return t

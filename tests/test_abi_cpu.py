@@ -130,6 +130,9 @@ def test_null_arguments(lib):
     (1, qfuse.make_tuning(mode=1, mem_save=1)),           # memory-saving mode is for fused plans
     (1, qfuse.make_tuning(epoch_fill=-2)),                # epoch threshold below -1
     (1, qfuse.make_tuning(epoch_fill=6)),                 # epoch threshold beyond the register
+    (1, qfuse.make_tuning(uncompute=2)),                  # uncompute is a flag
+    (1, qfuse.make_tuning(mode=1, uncompute=1)),          # uncompute is for fused plans
+    (1, qfuse.make_tuning(uncompute=1, mem_save=1)),      # nothing stored to compress
 ])
 def test_plan_validation_before_any_device_call(lib, batch, tuning):
     desc, _keep = _desc(2, [[RY, 0, -1, 0, -1], [CZ, 0, 1, -1, -1]])

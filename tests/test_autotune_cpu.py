@@ -67,3 +67,25 @@ def test_choose_storage_order():
 def test_tuning_from_mem_save():
     t = autotune.tuning_from({"tile_qubits": 12, "mem_save": 1})
     assert t.mem_save == 1 and t.mode == 0
+
+
+def test_tuning_from_uncompute_and_fill():
+    t = autotune.tuning_from({"uncompute": 1, "epoch_fill": -1, "ckpt_interval": 64})
+    assert (t.uncompute, t.epoch_fill, t.ckpt_interval, t.mem_save) == (1, -1, 64, 0)
+    t = autotune.tuning_from({})
+    assert (t.uncompute, t.epoch_fill) == (0, 0)
+
+
+def test_uncompute_storage():
+    """Uncompute mode: no stored pass outputs, so the workspace is the checkpoints plus four
+    micro-batch states; segments of at most UNCOMPUTE_MAX_SEGMENT passes when they fit."""
+    SB = 8 << 20
+    assert autotune.plan_states(253, 64, 1000, 128, True, False, True) == 4 * 1000 + 4 * 128
+    store, c = autotune.uncompute_storage(253, 1000, 128, SB, 200e9)
+    assert (store, c) == (1, autotune.UNCOMPUTE_MAX_SEGMENT)
+    # a tight budget: fewer, longer segments until the checkpoints fit
+    store, c = autotune.uncompute_storage(253, 1000, 128, SB, 3 * 1000 * SB + 4 * 128 * SB)
+    assert store == 1 and -(-253 // c) == 3
+    # not even one checkpoint of the whole batch fits: checkpoints per micro-batch
+    store, c = autotune.uncompute_storage(253, 1000, 128, SB, 1100 * SB)
+    assert store == 0 and c == autotune.UNCOMPUTE_MAX_SEGMENT

@@ -100,19 +100,29 @@ def test_hea16q200l_ce():
 
 
 @pytest.mark.timeout(900)
-def test_hea20q1000l_sampled():
+@pytest.mark.parametrize("config", ["default", "bench"])
+def test_hea20q1000l_sampled(config):
+    """Samples 0 and 1 against stored oracle values, with the default plan and
+    with the tuning bench.py times (the autotuned cache entry of this GPU)."""
     if not os.path.exists(GOLDEN):
         pytest.skip("stored oracle values not generated")
     g = np.load(GOLDEN)
     w = c4()
     dev = torch.device("cuda:0")
+    tun = None
+    if config == "bench":
+        from paper_2603_02804_amd import autotune
+        cached = autotune.cached_tuning(w.n_qubits, w.gates, w.n_obs, w.batch, autotune.device_key(dev))
+        if not cached:
+            pytest.skip("no autotuned configuration for this GPU")
+        tun = autotune.tuning_from(cached)
     circ = qfuse.Circuit(w.n_qubits, w.gates, w.n_params, w.n_inputs, w.zmask)
-    plan = qfuse.Plan(circ, w.batch)
+    plan = qfuse.Plan(circ, w.batch, tun)
     E, loss, dth, dx = ce_autograd(w, plan, dev)
     idx = list(g["samples"])
     assert np.abs(E.cpu().numpy()[idx] - g["E"]).max() <= E_TOL
     assert rel(dx[idx], g["dx"]) <= G_TOL
-    sub = qfuse.Plan(circ, len(idx))
+    sub = qfuse.Plan(circ, len(idx), tun)
     ws = sub.new_workspace(dev)
     th = torch.tensor(w.theta, device=dev)
     xs = torch.tensor(w.x[idx], device=dev)

@@ -56,7 +56,7 @@ def test_mem_save_mixed_batch_equals_single_plans():
     dev = torch.device("cuda:0")
     ws = mixed(6, (12, 15), (4, 8), 3, 41)
     xm, zm = z_observables([0])
-    tun = qfuse.make_tuning(ckpt_interval=2, mem_save=1)
+    tun = qfuse.make_tuning(ckpt_interval=2, mem_save=1, epoch_fill=-1)   # a batch's default threshold
     circs = [qfuse.Circuit(c.n_qubits, c.gates, len(c.theta), c.n_qubits, zm) for c in ws]
     thetas = [torch.tensor(c.theta, device=dev) for c in ws]
     xs = [torch.tensor(c.x, device=dev) for c in ws]

@@ -128,6 +128,19 @@ def test_general_gate_list(orc):
     compare(orc, n, gates, theta, x, [0, 5, 10], tile_qubits=8, reg_qubits=3, fusion_depth=2)
 
 
+@pytest.mark.parametrize("n,L,rots,B,tun", [
+    (13, 3, ("RX", "RY", "RZ"), 2, {}),
+    (14, 4, ("RX", "RY", "RZ"), 3, {"ckpt_interval": 2, "micro_batch": 2}),
+    (15, 4, ("RY", "RZ"), 2, {"store_ckpt": 0, "micro_batch": 1}),
+    (12, 5, ("RX", "RY", "RZ"), 4, {"tile_qubits": 8, "reg_qubits": 3, "fusion_depth": 2}),
+    (16, 12, ("RX", "RY", "RZ"), 2, {"ckpt_interval": 1000}),   # one segment: psi rebuilt through every pass
+])
+def test_uncompute(orc, n, L, rots, B, tun):
+    """The adjoint passes rebuild psi (no recompute, nothing stored in a segment)."""
+    gates, theta, x = hea_case(n, L, rots, B)
+    compare(orc, n, gates, theta, x, [0, 3, n - 1], uncompute=1, **tun)
+
+
 @pytest.mark.parametrize("fill", [-1, 1, 2, 0])
 def test_epoch_fill(orc, fill):
     """Each end-of-pass epoch threshold (a ring: partial epochs at pass ends are common)."""

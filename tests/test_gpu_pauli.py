@@ -39,6 +39,7 @@ def _run(n, gates, theta, x, xm, zm, dE, dtype=torch.float32, **tun):
     (12, 5, 2, dict(tile_qubits=11, reg_qubits=4)),
     (9, 6, 4, {}),
     (14, 3, 2, dict(mode=1)),
+    (15, 4, 2, dict(uncompute=1, ckpt_interval=2)),
 ])
 def test_pauli_against_oracle(n, L, B, tun):
     gates = hea_gates(n, L, ("RX", "RY", "RZ"))

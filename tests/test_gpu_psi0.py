@@ -24,6 +24,7 @@ def rel(a, b):
     (16, 3, 2, dict(store_ckpt=0, ckpt_interval=2, micro_batch=1)),
     (20, 2, 2, {}),
     (10, 4, 2, dict(mode=1)),
+    (15, 4, 2, dict(uncompute=1, ckpt_interval=2)),
 ])
 def test_paper_mode_against_oracle(n, L, B, tun):
     dev = torch.device("cuda:0")

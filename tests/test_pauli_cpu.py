@@ -22,6 +22,7 @@ def rel(a, b):
     (14, 3, 0, {}),
     (14, 3, 0, dict(ckpt_interval=1, micro_batch=1)),
     (13, 5, 0, dict(mem_save=1, ckpt_interval=2)),
+    (13, 5, 0, dict(uncompute=1, ckpt_interval=2)),
     (9, 4, 0, {}),
     (10, 2, 1, {}),
 ])

@@ -129,3 +129,42 @@ def test_epoch_fill_trades_epochs_for_passes():
     off = pc.stats(20, g, 3600, 20, [1], 8, epoch_fill=-1)
     on = pc.stats(20, g, 3600, 20, [1], 8)
     assert on["perm"] <= off["perm"] and on["passes"] <= off["passes"] + 2
+
+
+@pytest.mark.parametrize("n,L,rots,B,tun", [
+    (13, 3, ("RX", "RY", "RZ"), 2, {}),
+    (14, 4, ("RX", "RY", "RZ"), 3, {"ckpt_interval": 2, "micro_batch": 2}),
+    (15, 4, ("RY", "RZ"), 2, {"store_ckpt": 0, "micro_batch": 1}),
+    (12, 5, ("RX", "RY", "RZ"), 4, {"tile_qubits": 8, "reg_qubits": 3, "fusion_depth": 2}),
+    (10, 5, ("RX", "RY", "RZ"), 3, {"tile_qubits": 8, "reg_qubits": 4, "ckpt_interval": 2, "micro_batch": 2}),
+])
+def test_uncompute_programs(orc, n, L, rots, B, tun):
+    """The adjoint passes write psi at their input, so the backward recomputes
+    nothing; results match the oracle (and the recompute scheme)."""
+    gates = hea_gates(n, L, rots)
+    theta, x, _ = draw_inputs(41, L * len(rots) * n, B, n)
+    check(orc, n, gates, theta, x, [0, 3, n - 1], uncompute=1, **tun)
+
+
+def test_uncompute_drift_over_one_long_segment(orc):
+    """psi rebuilt through 16 fused passes (60 layers, one checkpoint segment):
+    the float32 drift of the reconstruction stays far inside the tolerance."""
+    n, L, B = 14, 60, 2
+    gates = hea_gates(n, L, ("RX", "RY", "RZ"))
+    theta, x, _ = draw_inputs(8, L * 3 * n, B, n)
+    xm, zm = z_observables([0, 3, n - 1])
+    dE = np.random.default_rng(1).normal(size=(B, 3)).astype(np.float32)
+    Eo, dtho, dxo = orc.backward(n, gates, theta, x, xm, zm, dE)
+    st = pc.stats(n, gates, len(theta), n, zm, B, uncompute=1, ckpt_interval=1000)
+    assert st["segments"] == 1 and st["passes"] > 10
+    E, dth, dx = pc.run(n, gates, theta, x, zm, dE, uncompute=1, ckpt_interval=1000)
+    assert np.linalg.norm(dth - dtho) / np.linalg.norm(dtho) <= 1e-4
+    assert np.linalg.norm(dx - dxo) / np.linalg.norm(dxo) <= 1e-4
+
+
+def test_uncompute_workspace_holds_no_segment_states():
+    g = hea_gates(16, 40, ("RX", "RY", "RZ"))
+    rec = pc.stats(16, g, 40 * 48, 16, [1], 8, ckpt_interval=4, micro_batch=4)
+    unc = pc.stats(16, g, 40 * 48, 16, [1], 8, ckpt_interval=4, micro_batch=4, uncompute=1)
+    SB = 8 << 16
+    assert rec["ws_bytes"] - unc["ws_bytes"] >= 3 * 4 * SB   # (ckpt - 1) x micro-batch stored outputs

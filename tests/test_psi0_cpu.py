@@ -20,6 +20,7 @@ def rel(a, b):
     (13, 3, 2, {}),
     (14, 4, 2, dict(ckpt_interval=1, micro_batch=1)),
     (14, 4, 3, dict(store_ckpt=0, ckpt_interval=2, micro_batch=2)),
+    (14, 4, 3, dict(uncompute=1, ckpt_interval=2, micro_batch=2)),
     (8, 3, 2, dict(mode=1)),
 ])
 def test_paper_mode_against_oracle(n, L, B, tun):
