@@ -352,7 +352,8 @@ def bench_mixed(args, dev) -> int:
     xs = [torch.tensor(c.x, device=dev) for c in ws]
     dEs = [torch.ones(s, 1, device=dev) for s in samples]
     t0 = time.perf_counter()
-    batch = qfuse.Batch(circs, samples, qfuse.make_tuning(epoch_fill=args.epoch_fill) if args.epoch_fill else None)
+    unc = 1 if args.uncompute is None else args.uncompute
+    batch = qfuse.Batch(circs, samples, qfuse.make_tuning(epoch_fill=args.epoch_fill, uncompute=unc))
     t_create = time.perf_counter() - t0
     info = batch.info
     wsb = batch.new_workspace(dev)
@@ -385,7 +386,7 @@ def bench_mixed(args, dev) -> int:
                    "circuits": len(ws), "samples": n_samples, "fwd_launches": int(info.fwd_launches),
                    "bwd_launches": int(info.bwd_launches), "fwd_jobs": int(info.fwd_jobs),
                    "bwd_jobs": int(info.bwd_jobs), "fwd_steps": int(info.fwd_steps),
-                   "bwd_steps": int(info.bwd_steps), "create_s": round(t_create, 2)},
+                   "bwd_steps": int(info.bwd_steps), "uncompute": unc, "create_s": round(t_create, 2)},
     }
     flops = info.fwd_flops + info.bwd_flops
     byts = info.fwd_bytes + info.bwd_bytes

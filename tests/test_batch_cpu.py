@@ -25,6 +25,7 @@ def _dEs(ws, seed):
     dict(n=4, qubits=(12, 13), layers=(3, 6), samples=5, seed=13, tuning=dict(micro_batch=2, ckpt_interval=3)),
     dict(n=4, qubits=(12, 14), layers=(4, 8), samples=3, seed=14, tuning=dict(ckpt_interval=2, mem_save=1)),
     dict(n=4, qubits=(13, 15), layers=(4, 7), samples=2, seed=15, tuning=dict(epoch_fill=4)),
+    dict(n=5, qubits=(11, 15), layers=(3, 7), samples=2, seed=16, tuning=dict(uncompute=1, ckpt_interval=2)),
 ])
 def test_batch_replay_equals_single(case):
     ws = mixed(case["n"], case["qubits"], case["layers"], case["samples"], case["seed"])

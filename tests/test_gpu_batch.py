@@ -26,10 +26,10 @@ def _setup(ws, dev, seed=0):
     return circs, thetas, xs, dEs, xm, zm
 
 
-def _single(circs, ws, thetas, xs, dEs, dev):
+def _single(circs, ws, thetas, xs, dEs, dev, **tun):
     out = []
     for c, w, t, x, d in zip(circs, ws, thetas, xs, dEs):
-        plan = qfuse.Plan(c, w.x.shape[0], qfuse.make_tuning(epoch_fill=-1))   # a batch's default
+        plan = qfuse.Plan(c, w.x.shape[0], qfuse.make_tuning(epoch_fill=-1, **tun))   # a batch's default
         wsb = plan.new_workspace(dev)
         E = plan.forward(t, x, wsb)
         dth, dx = plan.backward(t, x, d, wsb)
@@ -68,6 +68,25 @@ def test_batch_modes_equal_single_plans(mode):
         Eo = orc.forward(w.n_qubits, w.gates, w.theta, w.x, xm, zm)
         _, dtho, dxo = orc.backward(w.n_qubits, w.gates, w.theta, w.x, xm, zm, d.cpu().numpy().astype(np.float64))
         assert np.abs(E - Eo).max() <= 1e-4
+        assert np.abs(dth - dtho).max() <= 1e-3 * np.abs(dtho).max()
+        assert np.abs(dx - dxo).max() <= 1e-3 * np.abs(dxo).max()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_uncompute_equals_single_plans(mode):
+    """Uncompute mode in a mixed batch: the adjoint passes rebuild psi."""
+    dev = torch.device("cuda:0")
+    ws = mixed(8, (9, 15), (3, 8), 2, 33)
+    circs, thetas, xs, dEs, xm, zm = _setup(ws, dev, seed=2)
+    ref = _single(circs, ws, thetas, xs, dEs, dev, uncompute=1, ckpt_interval=2)
+    batch = qfuse.Batch(circs, [w.x.shape[0] for w in ws], qfuse.make_tuning(uncompute=1, ckpt_interval=2),
+                        launch_mode=mode)
+    wsb = batch.new_workspace(dev)
+    _same(_batch(batch, thetas, xs, dEs, wsb), ref)
+    orc = Oracle()
+    for w, (E, dth, dx), d in zip(ws, ref, dEs):
+        _, dtho, dxo = orc.backward(w.n_qubits, w.gates, w.theta, w.x, xm, zm, d.cpu().numpy().astype(np.float64))
         assert np.abs(dth - dtho).max() <= 1e-3 * np.abs(dtho).max()
         assert np.abs(dx - dxo).max() <= 1e-3 * np.abs(dxo).max()
 
