@@ -285,7 +285,7 @@ def bench_paper(args, dev) -> int:
     xm, zm = pauli_string(("IXYZ" * 5)[:n])
     circ = qfuse.Circuit(n, gates, L * 3 * n, 0, [zm], [xm])
     unc = 1 if args.uncompute is None else args.uncompute
-    tun = qfuse.make_tuning(micro_batch=args.micro_batch or 128, fusion_depth=args.fusion_depth,
+    tun = qfuse.make_tuning(micro_batch=args.micro_batch or 512, fusion_depth=args.fusion_depth,
                             ckpt_interval=args.ckpt_interval, tile_qubits=args.tile_qubits,
                             reg_qubits=args.reg_qubits, epoch_fill=args.epoch_fill, uncompute=unc)
     probe = qfuse.Plan(circ, B, tun)
