@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.timeout(300)
 @pytest.mark.parametrize("n,L,tun", [(14, 6, dict(ckpt_interval=2, micro_batch=2)), (9, 4, {}),
-                                     (13, 5, dict(mem_save=1, ckpt_interval=2))])
+                                     (13, 5, dict(mem_save=1, ckpt_interval=2)),
+                                     (14, 5, dict(uncompute=1, ckpt_interval=2))])
 def test_plan_graph_replays(n, L, tun):
     dev = torch.device("cuda:0")
     B = 4
