@@ -10,7 +10,10 @@ with P passes, segments of c passes, a batch B whose checkpoints are kept and a
 micro-batch mb recomputed at a time,
     states(c) = ceil(P / c) B + (c - 1) mb + 4 mb,
 minimised near c* = sqrt(P B / mb); the exact byte count is the plan's
-qf_workspace_size.
+qf_workspace_size.  In the uncompute mode (the adjoint passes rebuild psi)
+the (c - 1) mb term vanishes, and segments are kept to at most
+UNCOMPUTE_MAX_SEGMENT passes, which bounds the float32 drift of the rebuilt
+states, as long as the checkpoints fit.
 
 Speed: for each candidate (tile qubits, register qubits, fusion depth) the tuner
 builds a plan for a prefix of the gate list, times forward + backward with HIP
