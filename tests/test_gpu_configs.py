@@ -100,10 +100,12 @@ def test_hea16q200l_ce():
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("config", ["default", "bench"])
+@pytest.mark.parametrize("config", ["default", "bench", "uncompute_one_segment"])
 def test_hea20q1000l_sampled(config):
-    """Samples 0 and 1 against stored oracle values, with the default plan and
-    with the tuning bench.py times (the autotuned cache entry of this GPU)."""
+    """Samples 0 and 1 against stored oracle values, with the default plan, with
+    the tuning bench.py times (the autotuned cache entry of this GPU), and with
+    the adjoint passes rebuilding psi through all 1000 layers from the final
+    state (one checkpoint segment: the longest float32 reconstruction)."""
     if not os.path.exists(GOLDEN):
         pytest.skip("stored oracle values not generated")
     g = np.load(GOLDEN)
@@ -116,11 +118,14 @@ def test_hea20q1000l_sampled(config):
         if not cached:
             pytest.skip("no autotuned configuration for this GPU")
         tun = autotune.tuning_from(cached)
+    elif config == "uncompute_one_segment":
+        tun = qfuse.make_tuning(uncompute=1, ckpt_interval=100000, micro_batch=128)
     circ = qfuse.Circuit(w.n_qubits, w.gates, w.n_params, w.n_inputs, w.zmask)
     plan = qfuse.Plan(circ, w.batch, tun)
     E, loss, dth, dx = ce_autograd(w, plan, dev)
     idx = list(g["samples"])
     assert np.abs(E.cpu().numpy()[idx] - g["E"]).max() <= E_TOL
+    print(f"{config}: |dE| {np.abs(E.cpu().numpy()[idx] - g['E']).max():.2e}, dx {rel(dx[idx], g['dx']):.2e}")
     assert rel(dx[idx], g["dx"]) <= G_TOL
     sub = qfuse.Plan(circ, len(idx), tun)
     ws = sub.new_workspace(dev)
@@ -128,6 +133,7 @@ def test_hea20q1000l_sampled(config):
     xs = torch.tensor(w.x[idx], device=dev)
     sub.forward(th, xs, ws)
     dth2, _ = sub.backward(th, xs, torch.tensor(g["dE"], dtype=torch.float32, device=dev), ws)
+    print(f"{config}: dtheta {rel(dth2.cpu().numpy(), g['dtheta']):.2e}")
     assert rel(dth2.cpu().numpy(), g["dtheta"]) <= G_TOL
 
 
