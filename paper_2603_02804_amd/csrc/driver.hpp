@@ -379,32 +379,10 @@ qf_status run_backward_fused(const PlanCore& c, Exec& ex, const float* theta, co
     int li = 0;
     for (int s = c.n_seg - 1; s >= 0; --s) {
       const int a = c.seg_begin[s], b = c.seg_begin[s + 1];
-      if (c.uncompute) {
-        // the adjoint passes rebuild psi from the segment's checkpointed output
-        // (ping-pong through the work states); nothing is recomputed or stored
-        for (int p = b - 1; p >= a; --p) {
-          PassLaunch L;
-          L.pass = p;
-          L.bwd = true;
-          L.nb = nb;
-          L.sample0 = mb0;
-          if (p == b - 1) { L.src0 = ck + s * SA; L.src0_stride = ck_stride; }
-          else { L.src0 = work + (p & 1) * SA * nb; L.src0_stride = SA; }
-          if (p == c.P - 1 && c.S.general_obs)
-            ex.pauli_seed((const float*)(ck + s * SA), ck_stride, lam + li * SA * nb, SA, nb, mb0, dE);
-          if (p != c.P - 1 || c.S.general_obs) { L.src1 = lam + li * SA * nb; L.src1_stride = SA; }
-          if (p > 0) { L.dst = lam + (1 - li) * SA * nb; L.dst_stride = SA; }
-          if (p > a) { L.dpsi = work + ((p - 1) & 1) * SA * nb; L.dpsi_stride = SA; }
-          L.partF = partF + int64_t(nb) * c.partF_off[p];
-          L.dE = dE;
-          ex.pass(L);
-          li = 1 - li;
-        }
-        ex.assemble(s, nb, mb0, theta, x, partF, Gr);
-        continue;
-      }
-      // recompute the segment, storing every pass output but the last
-      for (int p = a; p <= b - 2; ++p) {
+      // recompute the segment, storing every pass output but the last (in the
+      // uncompute mode the adjoint passes rebuild psi instead, from the
+      // segment's checkpointed output through the work states)
+      for (int p = a; p <= b - 2 && !c.uncompute; ++p) {
         PassLaunch L;
         L.pass = p;
         L.nb = nb;
@@ -440,11 +418,13 @@ qf_status run_backward_fused(const PlanCore& c, Exec& ex, const float* theta, co
         L.nb = nb;
         L.sample0 = mb0;
         if (p == b - 1) { L.src0 = ck + s * SA; L.src0_stride = ck_stride; }
+        else if (c.uncompute) { L.src0 = work + (p & 1) * SA * nb; L.src0_stride = SA; }
         else { L.src0 = seg + int64_t(p - a) * SS; L.src0_stride = SS * (c.ckpt - 1); L.src0_bf16 = bf; }
         if (p == c.P - 1 && c.S.general_obs)   // seed from the stored output state
           ex.pauli_seed((const float*)(ck + s * SA), ck_stride, lam + li * SA * nb, SA, nb, mb0, dE);
         if (p != c.P - 1 || c.S.general_obs) { L.src1 = lam + li * SA * nb; L.src1_stride = SA; }
         if (p > 0) { L.dst = lam + (1 - li) * SA * nb; L.dst_stride = SA; }
+        if (c.uncompute && p > a) { L.dpsi = work + ((p - 1) & 1) * SA * nb; L.dpsi_stride = SA; }
         L.partF = partF + int64_t(nb) * c.partF_off[p];
         L.dE = dE;
         ex.pass(L);
