@@ -16,6 +16,11 @@ Sources of truth (none is the oracle itself):
   P9  Pauli-string expectation vs the dense Pauli product                 (App. B.2)
   P10 CNOT: the truth table on basis states, the Bell-state closed forms and the
       parameter shift through CNOT ladders (P5 and P6 also draw CNOT gates)
+  P11 caller-supplied initial states: dense products from psi0, and the parameter
+      shift of dense expectations from psi0                                (Sec. 4)
+  L1  the loss readings (sum, mean over observables, mean cross-entropy) against
+      closed forms, the two-class logistic special case, invariants and finite
+      differences; these pins take the loss helper instead of the oracle library
 """
 from __future__ import annotations
 
@@ -349,6 +354,122 @@ def pin_p10_cnot(orc):
         assert abs(dth[p] - (ep - em) / 2) < 1e-10
 
 
+# ---------------------------------------------------------------- P11
+def _random_states(rng, B, n):
+    psi = rng.standard_normal((B, 1 << n)) + 1j * rng.standard_normal((B, 1 << n))
+    return psi / np.linalg.norm(psi, axis=1, keepdims=True)
+
+
+def pin_p11_initial_states(orc):
+    """Caller-supplied initial states psi0[b] (Sec. 4 starts every experiment from
+    random states).  Per sample b, the final state is the dense circuit product
+    applied to psi0[b] (so the per-sample offset, the interleaving of real and
+    imaginary parts and the absence of a conjugate are all fixed), the
+    expectations of the forward and of the backward are <psi|O|psi> of that
+    state, and the backward gradients equal the parameter shift of expectations
+    formed from dense products from the same psi0[b]."""
+    rng = np.random.default_rng(11)
+    for n in (2, 3, 5):
+        gates = hea_gates(n, 2, ("RX", "RY", "RZ"), encoding=True, ring=n > 2)
+        P = 2 * 3 * n
+        theta = rng.uniform(0, 2 * math.pi, size=P)
+        B = 3
+        x = rng.uniform(-math.pi, math.pi, size=(B, n))
+        psi0 = _random_states(rng, B, n)
+        spec = ("IXYZ" * 2)[:n]
+        xm, zm = pauli_string(spec)
+        xms, zms = np.array([xm, 0], np.uint64), np.array([zm, 1], np.uint64)
+        dense_obs = [_pauli_dense(spec), _pauli_dense("I" * (n - 1) + "Z")]
+        E, psi = orc.forward(n, gates, theta, x, xms, zms, psi0=psi0, return_state=True)
+
+        def dense_E(th, xb, p0):
+            v = dense_state(n, gates, th, xb, psi0=p0)
+            return np.array([np.vdot(v, O @ v).real for O in dense_obs])
+
+        for b in range(B):
+            ref = dense_state(n, gates, theta, x[b], psi0=psi0[b])
+            np.testing.assert_allclose(psi[b], ref, atol=1e-12)
+            np.testing.assert_allclose(E[b], dense_E(theta, x[b], psi0[b]), atol=1e-12)
+        g = rng.normal(size=(B, 2))
+        E1, dth, dx = orc.backward(n, gates, theta, x, xms, zms, g, psi0=psi0)
+        np.testing.assert_allclose(E1, E, atol=1e-12)
+        for p in range(0, P, 3):
+            tp, tm = theta.copy(), theta.copy()
+            tp[p] += math.pi / 2
+            tm[p] -= math.pi / 2
+            ref = sum(0.5 * float(g[b] @ (dense_E(tp, x[b], psi0[b]) - dense_E(tm, x[b], psi0[b])))
+                      for b in range(B))
+            np.testing.assert_allclose(dth[p], ref, atol=1e-11)
+        for b in range(B):
+            for f in range(n):
+                xp, xn = x[b].copy(), x[b].copy()
+                xp[f] += math.pi / 2
+                xn[f] -= math.pi / 2
+                ref = 0.5 * float(g[b] @ (dense_E(theta, xp, psi0[b]) - dense_E(theta, xn, psi0[b])))
+                np.testing.assert_allclose(dx[b, f], ref, atol=1e-11)
+
+
 ALL_PINS = [pin_p1_single_qubit, pin_p2_two_qubit, pin_p3_zero_angles, pin_p4_norm,
             pin_p5_dense, pin_p6_parameter_shift, pin_p7_backward_modes, pin_p9_pauli_expectation,
-            pin_p10_cnot]
+            pin_p10_cnot, pin_p11_initial_states]
+
+
+# ---------------------------------------------------------------- loss helper (L1)
+def pin_l1_losses(loss_and_grad_E):
+    """The loss readings of the benchmarks against closed forms and invariants, not
+    against a second copy of their formulas:
+      * sum:      L = sum of all E; dL/dE = 1.
+      * mean_sum: L = sum_b mean_k E; dL/dE = 1/K.
+      * ce:       equal logits give L = log K and dL/dE = (1/K - [k = y]) / B;
+                  with two classes the cross-entropy is the logistic loss
+                  log(1 + exp(E_other - E_y)) (numpy's logaddexp), with gradient
+                  -+sigmoid(E_other - E_y) / B; a constant added to one sample's
+                  logits changes nothing; the batch loss is the mean of the
+                  one-sample losses; every gradient row sums to 0; and dL/dE is
+                  the central finite difference of L in every entry (which fixes
+                  the 1/B of the mean)."""
+    rng = np.random.default_rng(13)
+    E = rng.normal(size=(5, 4))
+    L, g = loss_and_grad_E(E, "sum")
+    assert abs(L - E.sum()) <= 1e-12 and np.array_equal(g, np.ones_like(E))
+    L, g = loss_and_grad_E(E, "mean_sum")
+    assert abs(L - E.sum() / 4) <= 1e-12
+    np.testing.assert_allclose(g, np.full_like(E, 0.25), atol=0)
+    for K, B in ((3, 1), (10, 4)):
+        lab = rng.integers(0, K, size=B)
+        L, g = loss_and_grad_E(np.full((B, K), 0.37), "ce", lab)
+        assert abs(L - math.log(K)) <= 1e-12
+        ref = np.full((B, K), 1.0 / K)
+        ref[np.arange(B), lab] -= 1.0
+        np.testing.assert_allclose(g, ref / B, atol=1e-14)
+    B = 6
+    E2 = rng.normal(size=(B, 2)) * 2
+    lab = rng.integers(0, 2, size=B)
+    d = E2[np.arange(B), 1 - lab] - E2[np.arange(B), lab]
+    L, g = loss_and_grad_E(E2, "ce", lab)
+    assert abs(L - np.logaddexp(0.0, d).mean()) <= 1e-12
+    sig = 1.0 / (1.0 + np.exp(-d))
+    np.testing.assert_allclose(g[np.arange(B), lab], -sig / B, atol=1e-14)
+    np.testing.assert_allclose(g[np.arange(B), 1 - lab], sig / B, atol=1e-14)
+    K, B = 10, 7
+    E3 = rng.normal(size=(B, K))
+    lab = rng.integers(0, K, size=B)
+    L, g = loss_and_grad_E(E3, "ce", lab)
+    shift = E3 + rng.normal(size=(B, 1)) * 5
+    L2, g2 = loss_and_grad_E(shift, "ce", lab)
+    assert abs(L - L2) <= 1e-12
+    np.testing.assert_allclose(g, g2, atol=1e-14)
+    singles = [loss_and_grad_E(E3[b:b + 1], "ce", lab[b:b + 1])[0] for b in range(B)]
+    assert abs(L - float(np.mean(singles))) <= 1e-12
+    np.testing.assert_allclose(g.sum(axis=1), 0.0, atol=1e-15)
+    h = 1e-6
+    for b in range(B):
+        for k in range(K):
+            Ep, Em = E3.copy(), E3.copy()
+            Ep[b, k] += h
+            Em[b, k] -= h
+            fd = (loss_and_grad_E(Ep, "ce", lab)[0] - loss_and_grad_E(Em, "ce", lab)[0]) / (2 * h)
+            assert abs(g[b, k] - fd) <= 1e-8
+
+
+LOSS_PINS = [pin_l1_losses]

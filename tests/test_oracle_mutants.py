@@ -71,6 +71,16 @@ MUTANTS = [
     ("cnot_control_target_swapped", "else if (g[0] == QFO_CNOT) apply_cnot(psi, n, g[1], g[2]);",
      "else if (g[0] == QFO_CNOT) apply_cnot(psi, n, g[2], g[1]);", None),
     ("lambda_skips_cnot", "        apply_cnot(lam, n, g[1], g[2]);\n", "", None),
+    ("psi0_offset_forward", "init_state(psi, n, psi0 ? psi0 + 2 * dim * b : NULL);",
+     "init_state(psi, n, psi0 ? psi0 + dim * b : NULL);", 0),
+    ("psi0_offset_backward", "init_state(psi, n, psi0 ? psi0 + 2 * dim * b : NULL);",
+     "init_state(psi, n, psi0 ? psi0 + dim * b : NULL);", 1),
+    ("psi0_ignored_in_backward", "init_state(psi, n, psi0 ? psi0 + 2 * dim * b : NULL);",
+     "init_state(psi, n, NULL);", 1),
+    ("psi0_conjugated_load", "psi[i] = c_make(psi0_b[2 * i], psi0_b[2 * i + 1]);",
+     "psi[i] = c_make(psi0_b[2 * i], -psi0_b[2 * i + 1]);", None),
+    ("psi0_parts_swapped", "psi[i] = c_make(psi0_b[2 * i], psi0_b[2 * i + 1]);",
+     "psi[i] = c_make(psi0_b[2 * i + 1], psi0_b[2 * i]);", None),
     ("batch_sum_first_sample_only", "for (b = 0; b < B; ++b) acc += gth[(int64_t)b * n_params + p];",
      "for (b = 0; b < 1; ++b) acc += gth[(int64_t)b * n_params + p];", None),
 ]
