@@ -40,9 +40,12 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_2603_02804_amd", "csrc", f)
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="hea20q1000l", choices=("hea20q1000l", "mixed256", "paper20q1000l"),
-                    help="hea20q1000l: the headline 20-qubit, 1000-layer HEA; mixed256: 256 mixed circuits, "
-                         "one merged HIP graph vs per-circuit launches")
+    ap.add_argument("--workload", default="hea20q1000l",
+                    choices=("hea20q1000l", "hea16q200l", "hea12q100l", "mixed256", "paper20q1000l", "hea_d1_sweep"),
+                    help="hea20q1000l: the headline 20-qubit, 1000-layer HEA (batch 1000); hea16q200l: 16 qubits, "
+                         "200 layers, batch 512; hea12q100l: 12 qubits, 100 layers, batch 1024; mixed256: 256 mixed "
+                         "circuits, one merged HIP graph vs per-circuit launches; paper20q1000l: the paper's Table 1 "
+                         "shape; hea_d1_sweep: one-layer HEA from random states, 4..20 qubits, fused vs per-gate")
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=0, help="override the batch (exploration only)")
@@ -81,9 +84,7 @@ def main() -> int:
               "(samples are independent, so a multi-GPU run would shard the batch and all-reduce dL/dtheta)",
               file=sys.stderr)
         return 2
-    import numpy as np
     import torch
-    import torch.nn.functional as Fnn
 
     if args.copy_calibration_mib:
         n = args.copy_calibration_mib << 20
@@ -95,19 +96,67 @@ def main() -> int:
         print(json.dumps({"copy_bytes": n}), flush=True)
         return 0
 
-    from paper_2603_02804_amd import qfuse
-    from paper_2603_02804_amd.workloads import c4, make_workload
-
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.workload == "mixed256":
         return bench_mixed(args, dev)
     if args.workload == "paper20q1000l":
         return bench_paper(args, dev)
-    if args.layers:
-        w = make_workload("hea20q", 20, args.layers, ("RX", "RY", "RZ"), 1000, tuple(range(10)), "ce", 4)
-    else:
-        w = c4()
+    if args.workload == "hea_d1_sweep":
+        return bench_sweep(args, dev)
+    return bench_hea(args, dev)
+
+
+def host_info() -> dict:
+    """The host the CPU baseline ran on: usable cores and the CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"nproc": nproc, "cpu_model": model}
+
+
+def hea_workload(name, layers=0):
+    from paper_2603_02804_amd.workloads import c2, c3, c4, make_workload
+    if name == "hea20q1000l" and layers:
+        return make_workload("hea20q", 20, layers, ("RX", "RY", "RZ"), 1000, tuple(range(10)), "ce", 4)
+    return {"hea12q100l": c2, "hea16q200l": c3, "hea20q1000l": c4}[name]()
+
+
+def metric_of(w) -> str:
+    if w.name == "hea20q1000l" and w.n_layers == 1000:
+        return METRIC
+    rots = "".join(r[1] for r in w.rotations)
+    return (f"samples/s fwd+adjoint grad ({w.n_qubits}q×{w.n_layers}L HEA, R{rots} + CZ ladder) fused vs per-gate; "
+            "HBM GB/s % peak")
+
+
+def describe(w) -> str:
+    rots = ",".join(w.rotations)
+    loss = (f"<Z_0..Z_{w.n_obs - 1}> -> {w.n_obs}-class CE" if w.loss == "ce"
+            else f"mean of <Z_i> over {w.n_obs} qubits, summed over the batch")
+    return (f"{w.name}: {w.n_qubits}-qubit HEA, {w.n_layers} layers of {rots} + CZ ladder, {w.n_params} angles, "
+            f"RY encoding of {w.n_inputs} features, {loss}")
+
+
+def bench_hea(args, dev) -> int:
+    """One of the HEA configurations: fused forward, loss in torch, fused adjoint backward."""
+    import numpy as np
+    import torch
+    import torch.nn.functional as Fnn
+
+    from paper_2603_02804_amd import qfuse
+
+    w = hea_workload(args.workload, args.layers)
     B = args.batch or w.batch
     x_np = w.x[:B]
     lab_np = w.labels[:B]
@@ -131,11 +180,16 @@ def main() -> int:
     x = torch.tensor(x_np, device=dev, requires_grad=True)
     labels = torch.tensor(lab_np, device=dev)
 
+    def loss_of(E, lab):
+        if w.loss == "ce":
+            return Fnn.cross_entropy(E, lab)
+        return E.mean(dim=1).sum()
+
     def step():
         theta.grad = None
         x.grad = None
         E = qfuse.circuit_expectations(theta, x, plan)
-        loss = Fnn.cross_entropy(E, labels)
+        loss = loss_of(E, labels)
         loss.backward()
         return loss
 
@@ -158,11 +212,13 @@ def main() -> int:
     # dominant kernel: the fused adjoint pass
     n_bwd = int(prof.launches[1])
     bwd_s = prof.ms[1] / 1000.0
+    n_fwd = int(prof.launches[0])
+    fwd_s = prof.ms[0] / 1000.0
     flops_bwd = info.bwd_pass_flops_per_sample * B * args.steps
     bytes_bwd = info.bwd_pass_bytes_per_sample * B * args.steps
     achieved_tf = flops_bwd / bwd_s / 1e12 if bwd_s > 0 else 0.0
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    if os.path.exists(TRAFFIC_FILE) and w.name == "hea20q1000l":
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         # per-sample bytes depend on the pass structure, not on how samples are grouped into micro-batches
@@ -183,21 +239,29 @@ def main() -> int:
         "flops_per_launch": flops_bwd / max(1, n_bwd), "bytes_per_launch": bytes_bwd / max(1, n_bwd),
         "hbm_gbs": round(bytes_bwd / bwd_s / 1e9, 1) if bwd_s > 0 else 0.0,
     }
+    # the forward pass kernel beside it (16 algorithmic flops per run-amplitude, 6 executed)
+    fwd_flops = info.fwd_flops_per_sample * B * args.steps
+    fwd_tf = fwd_flops / fwd_s / 1e12 if fwd_s > 0 else 0.0
+    fwd_roof = {"kernel": f"k_pass<{info.reg_qubits},{info.threads},false> (fused forward pass)",
+                "achieved": round(fwd_tf, 2), "frac": round(fwd_tf / PEAK_FP32_TFLOPS, 4),
+                "executed_tflops": round(fwd_tf * 6 / 16, 2), "launches": n_fwd,
+                "avg_launch_ms": round(prof.ms[0] / max(1, n_fwd), 4),
+                "hbm_gbs": round(info.fwd_bytes_per_sample * B * args.steps / fwd_s / 1e9, 1) if fwd_s > 0 else 0.0}
     step_bytes = (info.fwd_bytes_per_sample + info.bwd_bytes_per_sample) * B
     hbm_gbs = step_bytes / (elapsed / args.steps) / 1e9
     kernel_share = {"fwd_pass_ms": round(prof.ms[0] / args.steps, 1), "bwd_pass_ms": round(prof.ms[1] / args.steps, 1),
                     "other_ms": round(prof.ms[2] / args.steps, 1)}
     out = {
-        "metric": METRIC, "value": round(value, 3), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "metric": metric_of(w), "value": round(value, 3), "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 1), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"hea20q{w.n_layers}l: 20-qubit HEA, {w.n_layers} layers of RX,RY,RZ + CZ ladder, "
-                               f"{w.n_params} angles, RY encoding of 20 features, <Z_0..Z_9> -> 10-class CE",
+        "config": {"workload": describe(w) if not args.layers else f"{w.name}{w.n_layers}l (depth override)",
                    "batch": B, "micro_batch": info.micro_batch, "tile_qubits": info.tile_qubits,
                    "reg_qubits": info.reg_qubits, "fusion_depth": info.fusion_depth, "fused_passes": info.fused_passes,
                    "ckpt_interval": info.ckpt_interval, "segments": info.segments, "epoch_fill": info.epoch_fill,
                    "uncompute": info.uncompute, "tuning": tuning_src},
         "roofline": roofline,
+        "forward_pass": fwd_roof,
         "hbm": {"gbs": round(hbm_gbs, 1), "frac": round(hbm_gbs / PEAK_HBM_GBS, 4),
                 "bytes_per_sample": info.fwd_bytes_per_sample + info.bwd_bytes_per_sample},
         "kernel_time_per_step": kernel_share,
@@ -216,7 +280,7 @@ def main() -> int:
         def pg_step():
             E = pg_plan.forward(th2, x2, ws)
             Ev = E.clone().requires_grad_(True)
-            Fnn.cross_entropy(Ev, lab2).backward()
+            loss_of(Ev, lab2).backward()
             pg_plan.backward(th2, x2, Ev.grad, ws)
 
         pg_step()
@@ -233,30 +297,43 @@ def main() -> int:
                            # the unfused kernels are HBM-bound: their algorithmic bytes over time
                            "hbm_gbs": round(pg_gbs, 1), "hbm_frac": round(pg_gbs / PEAK_HBM_GBS, 4)}
         del ws
-        # CPU oracle on the host cores: one sample, the first L layers, extrapolated in depth
-        from oracle.oracle import Oracle, loss_and_grad_E
-        from paper_2603_02804_amd.workloads import hea_gates
-        orc = Oracle()
-        n = w.n_qubits
-
-        def cpu_time(L):
-            g = hea_gates(n, L, ("RX", "RY", "RZ"))
-            P = L * 3 * n
-            _, gE = loss_and_grad_E(np.zeros((1, w.n_obs)), "ce", lab_np[:1])
-            t = time.perf_counter()
-            orc.backward(n, g, w.theta[:P], x_np[:1], w.xmask, w.zmask, gE)
-            return time.perf_counter() - t
-
-        t1l = cpu_time(1)
-        Ls = int(max(1, min(w.n_layers, round(args.cpu_seconds / max(t1l, 1e-3)))))
-        tL = cpu_time(Ls) if Ls > 1 else t1l
-        per_sample = tL * w.n_layers / Ls
-        out["cpu_baseline"] = {"value": round(1.0 / per_sample, 6), "unit": "samples/s", "cores": orc.num_threads,
-                               "kind": "oracle",
-                               "sample": f"1 sample, first {Ls} of {w.n_layers} layers ({tL:.1f} s), "
-                                         f"extrapolated linearly in depth"}
+        out["cpu_baseline"] = cpu_baseline_hea(w, x_np, lab_np, args.cpu_seconds)
     print(json.dumps(out), flush=True)
     return 0
+
+
+def cpu_baseline_hea(w, x_np, lab_np, budget_s):
+    """The complex128 oracle on the host cores: forward + adjoint gradient of a bounded sample of the
+    workload.  Full depth for as many samples as fit the time budget; a circuit too deep for one
+    sample in the budget is timed on its leading layers and extrapolated linearly in depth."""
+    import numpy as np
+
+    from oracle.oracle import Oracle, loss_and_grad_E
+    from paper_2603_02804_amd.workloads import hea_gates
+    orc = Oracle()
+    n, R = w.n_qubits, len(w.rotations)
+
+    def cpu_time(L, nb):
+        g = hea_gates(n, L, w.rotations)
+        _, gE = loss_and_grad_E(np.zeros((nb, w.n_obs)), w.loss, lab_np[:nb])
+        t = time.perf_counter()
+        orc.backward(n, g, w.theta[:L * R * n], x_np[:nb], w.xmask, w.zmask, gE)
+        return time.perf_counter() - t
+
+    t1l = cpu_time(1, 1)
+    if t1l * w.n_layers <= budget_s / 2:
+        t_full = cpu_time(w.n_layers, 1)
+        nb = int(max(1, min(len(x_np), budget_s // max(t_full, 1e-6))))
+        t = cpu_time(w.n_layers, nb) if nb > 1 else t_full
+        per_sample = t / nb
+        sample = f"{nb} samples at full depth ({t:.1f} s)"
+    else:
+        Ls = int(max(1, min(w.n_layers, round(budget_s / max(t1l, 1e-3)))))
+        tL = cpu_time(Ls, 1) if Ls > 1 else t1l
+        per_sample = tL * w.n_layers / Ls
+        sample = f"1 sample, first {Ls} of {w.n_layers} layers ({tL:.1f} s), extrapolated linearly in depth"
+    return {"value": round(1.0 / per_sample, 6), "unit": "samples/s", "cores": orc.num_threads, "kind": "oracle",
+            "sample": sample, "host": host_info()}
 
 
 # The paper's own 20-qubit, 1000-layer epoch (Table 1, fused, GH200): 1,000 samples in 1,273 s.
@@ -330,6 +407,85 @@ def bench_paper(args, dev) -> int:
                    "ckpt_interval": info.ckpt_interval, "segments": info.segments, "uncompute": info.uncompute,
                    "paper": "1,273 s per 1,000-sample epoch on GH200 (Table 1): 0.786 samples/s; context, "
                             "other hardware"},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def bench_sweep(args, dev) -> int:
+    """The paper's throughput experiment (Sec. 4.2): a one-layer HEA (RX, RY, RZ on every qubit, CZ ring)
+    applied to random initial states, observable (IXYZ) repeated over the register, L = sum of E;
+    forward + adjoint gradient, fused and per gate, for 4..20 qubits.  The batch per size is the largest
+    power of two up to 65536 whose states take at most 4 GiB (the paper takes the largest batch that fits
+    its GPU)."""
+    import numpy as np
+    import torch
+
+    from paper_2603_02804_amd import qfuse
+    from paper_2603_02804_amd.workloads import paper_mode
+
+    sizes = list(range(4, 21)) if not args.layers else [args.layers]
+    rows = []
+    for n in sizes:
+        B = args.batch or int(min(65536, max(64, (4 << 30) // (8 << n))))
+        w = paper_mode(n, 1, 1, seed=n)
+        g = torch.Generator(device=dev).manual_seed(n)
+        psi0 = torch.complex(torch.randn(B, 1 << n, generator=g, device=dev),
+                             torch.randn(B, 1 << n, generator=g, device=dev))
+        psi0 /= torch.linalg.vector_norm(psi0, dim=1, keepdim=True)
+        theta = torch.tensor(w.theta, device=dev)
+        circ = qfuse.Circuit(n, w.gates, len(w.theta), 0, w.zmask, w.xmask)
+        dE = torch.ones(B, 1, device=dev)
+
+        def timed(plan, nb, reps):
+            ws = plan.new_workspace(dev)
+            p0 = psi0[:nb]
+            d = dE[:nb]
+
+            def once():
+                plan.forward(theta, None, ws, psi0=p0)
+                plan.backward(theta, None, d, ws, psi0=p0)
+
+            once()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                once()
+            torch.cuda.synchronize()
+            sec = (time.perf_counter() - t) / reps
+            del ws
+            return sec
+
+        plan = qfuse.Plan(circ, B, qfuse.make_tuning(uncompute=1))
+        info = plan.info
+        sec = timed(plan, B, max(1, args.steps))
+        # algorithmic bytes of the call: the plan's passes plus the initial-state read
+        byts = (info.fwd_bytes_per_sample + info.bwd_bytes_per_sample + (8 << n)) * B
+        nb_pg = min(B, 4096)
+        pg = qfuse.Plan(circ, nb_pg, qfuse.make_tuning(mode=1, micro_batch=nb_pg))
+        pg_sec = timed(pg, nb_pg, 1)
+        pgi = pg.info
+        pg_bytes = (pgi.fwd_bytes_per_sample + pgi.bwd_bytes_per_sample + (8 << n)) * nb_pg
+        del plan, pg
+        row = {"n": n, "batch": B, "fused_passes": info.fused_passes, "fused": round(B / sec, 1),
+               "per_gate": round(nb_pg / pg_sec, 1), "speedup": round((B / sec) / (nb_pg / pg_sec), 2),
+               "fused_hbm_gbs": round(byts / sec / 1e9, 1), "fused_hbm_frac": round(byts / sec / 1e9 / PEAK_HBM_GBS, 4),
+               "per_gate_hbm_gbs": round(pg_bytes / pg_sec / 1e9, 1)}
+        rows.append(row)
+        print(json.dumps({"sweep_row": row}), file=sys.stderr, flush=True)
+        del psi0
+        torch.cuda.empty_cache()
+    last = rows[-1]
+    out = {
+        "metric": "samples/s fwd+adjoint grad, one-layer HEA (RX,RY,RZ + CZ ring) from random states, fused vs "
+                  "per-gate, 4..20 qubits",
+        "value": last["fused"], "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": round(1000 * last["batch"] / last["fused"], 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"hea_d1_sweep: one layer of RX,RY,RZ + CZ ring, random initial states, O = (IXYZ)... "
+                               f"over the register, L = sum E; value at {last['n']} qubits, batch {last['batch']}",
+                   "uncompute": 1},
+        "sweep": rows,
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -430,7 +586,7 @@ def bench_mixed(args, dev) -> int:
             cost_pick += cost(c)
         total = est * sum(cost(c) for c in ws) / cost_pick
         out["cpu_baseline"] = {"value": round(n_samples / total, 4), "unit": "samples/s",
-                               "cores": orc.num_threads, "kind": "oracle",
+                               "cores": orc.num_threads, "kind": "oracle", "host": host_info(),
                                "sample": f"8 circuits spread over the cost order, all 4 samples, leading layers "
                                          f"({spent:.1f} s), extrapolated in depth and by amplitudes x gates"}
     print(json.dumps(out), flush=True)

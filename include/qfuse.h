@@ -161,36 +161,74 @@ typedef struct {
 typedef struct qf_circuit qf_circuit;
 typedef struct qf_plan qf_plan;
 
-/* Validates and copies the description (host only).  Ownership of *out passes
-   to the caller; release with qf_circuit_destroy. */
+/*
+ * The parameterised circuit U(theta, x) = U_M ... U_1 of Sec. 2.1 as a gate
+ * list, with the observables O_k of the expectation values.  Validates and
+ * copies the description (host only; desc and its arrays stay the caller's).
+ * Errors: QF_ERR_INVALID_ARG for NULL pointers, qubit or angle indices out of
+ * range, a rotation with both or neither angle index, a two-qubit gate on one
+ * qubit; QF_ERR_UNSUPPORTED for n_qubits outside 1..30 or more than 64
+ * observables.  Ownership of *out passes to the caller; release with
+ * qf_circuit_destroy (NULL is accepted).
+ */
 qf_status qf_circuit_create(const qf_circuit_desc* desc, qf_circuit** out);
 qf_status qf_circuit_destroy(qf_circuit* circuit);
 
-/* Builds the pass schedule for `batch` samples and uploads its descriptor
-   tables to the current HIP device.  tuning may be NULL (defaults). */
+/*
+ * Builds the execution plan of a circuit for `batch` >= 1 samples: consecutive
+ * single-qubit gates on one qubit merged into runs, runs fused into passes that
+ * each read and write a sample's state once (forward and backward gate fusion,
+ * Sec. 3.2 and Sec. 3.3; fused CZ, App. B.1), and checkpoint segments of
+ * passes with the workspace they need (gradient checkpointing, Sec. 3.4, whose
+ * memory model is eq. mem_cap_proposed).  Uploads the plan's descriptor tables
+ * to the current HIP device, which the later calls must also use.  tuning may
+ * be NULL (defaults); it is copied.  Errors: QF_ERR_INVALID_ARG (NULL circuit or
+ * out, batch < 1, a tuning field out of range or an invalid combination),
+ * QF_ERR_UNSUPPORTED (no kernel for the tile shape, or a pass whose LDS exceeds
+ * the device limit: lower fusion_depth), QF_ERR_OOM (host or device allocation
+ * of the tables).  Ownership of *out passes to the caller; qf_plan_destroy
+ * frees the plan and its device tables (NULL is accepted).
+ */
 qf_status qf_plan_create(const qf_circuit* circuit, int32_t batch, const qf_tuning* tuning,
                          qf_plan** out);
 qf_status qf_plan_destroy(qf_plan* plan);
+/* Fills *info (host struct, caller-owned); QF_ERR_INVALID_ARG on NULL. */
 qf_status qf_plan_get_info(const qf_plan* plan, qf_plan_info* info);
 
-/* Device workspace (bytes, 256-byte aligned start expected) that qf_forward and
-   qf_backward need: checkpoints, stored pass outputs, adjoint states, partial
-   sums and coefficient tables. */
+/*
+ * Device workspace in bytes that qf_forward and qf_backward need: segment
+ * checkpoints and the stored pass outputs of one segment (Sec. 3.4, eq.
+ * mem_cap_proposed with fused passes in place of layers), forward and adjoint
+ * working states, partial sums and coefficient tables.  The caller allocates
+ * it (start 256-byte aligned) and owns it.  QF_ERR_INVALID_ARG on NULL.
+ */
 qf_status qf_workspace_size(const qf_plan* plan, size_t* bytes);
 
 /*
- * Forward pass.  theta: device float[n_params]; x: device float[batch][n_inputs]
- * (may be NULL when n_inputs == 0); E: device float[batch][n_obs], overwritten.
- * ws must stay untouched until the matching qf_backward has been enqueued.
+ * Forward pass: E[b][k] = <psi_M(b)| O_k |psi_M(b)> with psi_M(b) = U(theta,
+ * x_b) |0...0> (Sec. 2.1), the circuit applied in fused passes (Sec. 3.2).
+ * theta: device float[n_params]; x: device float[batch][n_inputs], row-major
+ * (may be NULL when n_inputs == 0); E: device float[batch][n_obs], row-major,
+ * overwritten.  ws: the caller's workspace of ws_bytes >= qf_workspace_size;
+ * it must stay untouched until the matching qf_backward has been enqueued.
+ * Errors: QF_ERR_INVALID_ARG (NULL plan or buffer, a plan of another device or
+ * a complex128 plan), QF_ERR_WORKSPACE (ws NULL, too small or misaligned),
+ * QF_ERR_DEVICE (a launch failed).
  */
 qf_status qf_forward(qf_plan* plan, const float* theta, const float* x, float* E,
                      void* ws, size_t ws_bytes, void* stream);
 
 /*
- * Backward pass: dE device float[batch][n_obs] = dL/dE.  Writes
+ * Backward pass by the adjoint method (Sec. 2.2): the adjoint state is seeded as
+ * lambda_M = 2 sum_k dE_k O_k psi_M (eq. bwd_exp_val with the chain rule), each
+ * angle's gradient is Re<lambda_j| dU_j/dphi |psi_{j-1}> (eq. grad_theta) and
+ * lambda is carried back by U_j^dagger (eq. update_adjoint_state), in fused
+ * adjoint passes (Sec. 3.3) over checkpoint segments (Sec. 3.4).
+ * dE: device float[batch][n_obs] = dL/dE, row-major.  Writes
  *   dtheta: device float[n_params] = sum over the batch (overwritten),
- *   dx:     device float[batch][n_inputs] (overwritten; may be NULL).
+ *   dx:     device float[batch][n_inputs], row-major (overwritten; may be NULL).
  * Needs the same ws, theta and x as the preceding qf_forward on this plan.
+ * Errors as qf_forward.
  */
 qf_status qf_backward(qf_plan* plan, const float* theta, const float* x, const float* dE,
                       float* dtheta, float* dx, void* ws, size_t ws_bytes, void* stream);
@@ -233,7 +271,7 @@ qf_status qf_backward_c128(qf_plan* plan, const double* theta, const double* x, 
                            double* dtheta, double* dx, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * Kernel timing for accounting.  While enabled, every launch the plan makes is
+ * Kernel timing for accounting (the measurements of Sec. 4 as per-kernel time).  While enabled, every launch the plan makes is
  * bracketed by HIP events recorded on the call's stream; qf_profile_read waits
  * for the recorded events, returns per-class launch counts and summed durations
  * (milliseconds) since the last read, and clears them.  Classes: 0 = fused
@@ -280,10 +318,14 @@ typedef struct {
 } qf_batch_info;
 
 /*
- * circuits[i] is simulated for samples[i] >= 1 samples.  tuning (may be NULL)
- * applies to every circuit's plan; mode must be 0 (fused); mem_save may be set.
- * Circuits whose observables have X or Y factors: QF_ERR_UNSUPPORTED.  The
- * plans and merged tables live on the current HIP device.
+ * circuits[i] is simulated for samples[i] >= 1 samples; each gets the plan that
+ * qf_plan_create would build (Sec. 3.2-3.4: runs fused into passes,
+ * checkpoint segments), and the plans' launch sequences are merged.  tuning
+ * (may be NULL) applies to every circuit's plan; mode must be 0 (fused);
+ * mem_save may be set.  Errors: QF_ERR_INVALID_ARG (NULL or empty arrays,
+ * samples < 1), QF_ERR_UNSUPPORTED (mode != 0, X or Y factors in an
+ * observable, or any qf_plan_create refusal, named by circuit index),
+ * QF_ERR_OOM.  The plans and merged tables live on the current HIP device.
  */
 qf_status qf_batch_create(const qf_circuit* const* circuits, const int32_t* samples, int32_t n_circuits,
                           const qf_tuning* tuning, qf_batch** out);
@@ -294,7 +336,8 @@ qf_status qf_batch_workspace_size(const qf_batch* batch, size_t* bytes);
 qf_status qf_batch_set_launch_mode(qf_batch* batch, int32_t mode);
 
 /*
- * Forward of every circuit.  theta, x and E are HOST arrays of n_circuits
+ * Forward of every circuit: qf_forward's expectations (Sec. 2.1) per circuit.
+ * theta, x and E are HOST arrays of n_circuits
  * DEVICE pointers: theta[i] float[n_params_i], x[i] float[samples_i][n_inputs_i]
  * (NULL allowed when n_inputs_i == 0), E[i] float[samples_i][n_obs_i],
  * overwritten.  The batch copies the pointer arrays before returning.
@@ -304,8 +347,9 @@ qf_status qf_batch_forward(qf_batch* batch, const float* const* theta, const flo
                            float* const* E, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * Backward of every circuit after qf_batch_forward with the same ws, theta and
- * x.  dE[i] float[samples_i][n_obs_i]; dtheta[i] float[n_params_i] (overwritten,
+ * Backward of every circuit: qf_backward's adjoint gradients (Sec. 2.2, eq.
+ * grad_theta, eq. update_adjoint_state) per circuit, after qf_batch_forward
+ * with the same ws, theta and x.  dE[i] float[samples_i][n_obs_i]; dtheta[i] float[n_params_i] (overwritten,
  * summed over the circuit's samples); dx may be NULL, or dx[i] NULL, or
  * dx[i] float[samples_i][n_inputs_i] (overwritten).
  */

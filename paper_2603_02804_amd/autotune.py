@@ -78,7 +78,13 @@ def optimal_ckpt(passes: int, batch: int, micro_batch: int, store: bool = True, 
 
 def uncompute_storage(passes: int, batch: int, micro_batch: int, state_bytes: int, budget: float):
     """(store_ckpt, ckpt_interval) of the uncompute mode: checkpoints for the whole batch every
-    UNCOMPUTE_MAX_SEGMENT passes, or fewer segments until they fit, else checkpoints per micro-batch."""
+    UNCOMPUTE_MAX_SEGMENT passes, or fewer segments until they fit, else checkpoints per micro-batch.
+
+    The segment cap bounds the float32 drift of the rebuilt states only while checkpoints fit at
+    that interval; under a tight budget the segments grow, up to one segment of all passes, whose
+    drift is the worst case (measured at 20 qubits x 1000 layers, 253 passes: normwise gradient
+    error 2.3e-5 against the oracle).  When nothing fits, the least-memory option is returned
+    (checkpoints per micro-batch, one segment), as choose_storage does."""
     c = min(passes, UNCOMPUTE_MAX_SEGMENT)
     for store in (1, 0):
         for ck in range(c, passes + 1):
@@ -86,7 +92,7 @@ def uncompute_storage(passes: int, batch: int, micro_batch: int, state_bytes: in
                 return store, ck
             if -(-passes // ck) == 1:
                 break
-    return 0, c
+    return 0, passes
 
 
 def choose_storage(passes: int, batch: int, micro_batch: int, state_bytes: int, budget: float):

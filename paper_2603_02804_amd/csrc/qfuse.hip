@@ -614,6 +614,24 @@ qf_status qf_plan_create(const qf_circuit* circuit, int32_t batch, const qf_tuni
     st = QF_ERR_UNSUPPORTED;
     msg = "no pass kernel for this tile shape";
   }
+  if (st == QF_OK && !p->core.per_gate) {
+    // LDS of a workgroup: the pass kernels' static tile plus the adjoint pass's
+    // per-wave functional sums (they grow with the runs fused into one pass),
+    // and the assembly kernel's per-run sums; a plan that would exceed the
+    // device limit is refused here rather than failing at launch
+    int dev = 0, lim = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lim <= 0)
+      lim = 64 << 10;
+    const PlanCore& c = p->core;
+    const size_t tile = sizeof(float2) * ((size_t)1 << c.S.R) * c.S.NT;
+    const size_t need = std::max(tile + pass_shmem(c, true), assemble_shmem(c));
+    if (need > (size_t)lim) {
+      st = QF_ERR_UNSUPPORTED;
+      msg = "a pass needs " + std::to_string(need) + " bytes of LDS per workgroup, the device allows " +
+            std::to_string(lim) + ": lower fusion_depth (fewer runs per pass)";
+    }
+  }
   if (st == QF_OK) {
     hipGetDevice(&p->device);
     st = upload_plan(p->core, &p->dev, &msg);

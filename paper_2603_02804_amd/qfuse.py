@@ -295,8 +295,9 @@ class Plan:
         self._check_inputs(theta, x)
         p0 = self._check_psi0(psi0)
         dE = dE.contiguous().to(self.dtype)
-        dtheta = torch.empty_like(theta)
-        dx = torch.empty_like(x) if (want_dx and x is not None) else None
+        # the library writes dense row-major outputs: allocate them so, whatever the inputs' strides
+        dtheta = torch.empty(theta.shape, dtype=self.dtype, device=theta.device)
+        dx = torch.empty(x.shape, dtype=self.dtype, device=x.device) if (want_dx and x is not None) else None
         s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
         xc = x.contiguous() if x is not None else None
         if self.c128:
@@ -329,22 +330,25 @@ class CircuitFunction(torch.autograd.Function):
         E = plan.forward(theta.detach(), x.detach() if x is not None else None, ws, psi0=psi0)
         ctx.plan = plan
         ctx.ws = ws
-        ctx.psi0 = psi0
-        ctx.save_for_backward(theta, x if x is not None else torch.empty(0, device=theta.device))
+        # psi0 is saved like the other inputs: the backward reads it again (the first
+        # segment's recompute), so an in-place change in between must raise
+        empty = torch.empty(0, device=theta.device)
+        ctx.save_for_backward(theta, x if x is not None else empty, psi0 if psi0 is not None else empty)
         ctx.has_x = x is not None
+        ctx.has_psi0 = psi0 is not None
         ctx.retain = bool(retain_workspace)
         return E
 
     @staticmethod
     def backward(ctx, gE):
-        theta, x = ctx.saved_tensors
+        theta, x, psi0 = ctx.saved_tensors
         x = x if ctx.has_x else None
+        psi0 = psi0 if ctx.has_psi0 else None
         want_dx = ctx.has_x and ctx.needs_input_grad[1]
         dtheta, dx = ctx.plan.backward(theta.detach(), x.detach() if x is not None else None, gE, ctx.ws,
-                                       want_dx=want_dx, psi0=ctx.psi0)
+                                       want_dx=want_dx, psi0=psi0)
         if not ctx.retain:
             ctx.ws = None
-            ctx.psi0 = None
         return dtheta, dx, None, None, None
 
 

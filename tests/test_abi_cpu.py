@@ -145,3 +145,24 @@ def test_plan_validation_before_any_device_call(lib, batch, tuning):
         assert h.value is None
     finally:
         lib.qf_circuit_destroy(circ)
+
+
+def test_plan_refused_when_a_pass_exceeds_the_lds_limit(lib):
+    """A fusion depth that puts thousands of runs into one pass would need more LDS
+    per adjoint-pass workgroup (per-wave functional sums) than any device has: the
+    plan is refused at creation (host-side check, before any upload or launch)."""
+    from paper_2603_02804_amd.workloads import hea_gates
+    n, L = 12, 2000
+    gates = hea_gates(n, L, ("RY",), encoding=False)
+    desc, _keep = _desc(n, gates, P=n * L)
+    st, circ = _create(lib, desc)
+    assert st == QF_OK
+    try:
+        h = ctypes.c_void_p()
+        t = qfuse.make_tuning(tile_qubits=12, reg_qubits=4, fusion_depth=L)
+        st = lib.qf_plan_create(circ, 1, ctypes.byref(t), ctypes.byref(h))
+        assert st == UNSUPPORTED, lib.qf_last_error()
+        assert h.value is None
+        assert b"LDS" in lib.qf_last_error()
+    finally:
+        lib.qf_circuit_destroy(circ)

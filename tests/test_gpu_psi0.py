@@ -44,6 +44,29 @@ def test_paper_mode_against_oracle(n, L, B, tun):
     assert rel(dth.cpu().numpy(), dtho) <= G_TOL
 
 
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n,B", [(4, 64), (5, 33), (8, 16), (12, 8), (13, 4)])
+def test_hea_d1_sweep_shapes_against_oracle(n, B):
+    """The one-layer HEA of the throughput sweep (RX, RY, RZ + CZ ring from random states, (IXYZ)...,
+    L = sum E) in the plan the benchmark uses (adjoint passes rebuild psi), fused and per gate."""
+    dev = torch.device("cuda:0")
+    w = paper_mode(n, 1, B, seed=100 + n)
+    circ = qfuse.Circuit(n, w.gates, len(w.theta), 0, w.zmask, w.xmask)
+    th = torch.tensor(w.theta, device=dev)
+    psi0 = torch.tensor(w.psi0, device=dev)
+    dE = torch.ones(B, 1, device=dev)
+    Eo, dtho, _ = Oracle().backward(n, w.gates, w.theta, np.zeros((B, 0)), w.xmask, w.zmask, np.ones((B, 1)),
+                                    psi0=w.psi0)
+    for tun in (qfuse.make_tuning(uncompute=1), qfuse.make_tuning(mode=1, micro_batch=B)):
+        plan = qfuse.Plan(circ, B, tun)
+        ws = plan.new_workspace(dev)
+        E = plan.forward(th, None, ws, psi0=psi0)
+        dth, _ = plan.backward(th, None, dE, ws, psi0=psi0)
+        torch.cuda.synchronize()
+        assert np.abs(E.cpu().numpy() - Eo).max() <= E_TOL
+        assert rel(dth.cpu().numpy(), dtho) <= G_TOL
+
+
 def test_paper_mode_c128_gradcheck():
     dev = torch.device("cuda:0")
     n, L, B = 4, 2, 2
