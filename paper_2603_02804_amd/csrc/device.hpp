@@ -61,24 +61,10 @@ __device__ __forceinline__ CzGroup ld_czg(const CzGroup* p) {
     default: break;                                  \
   }
 
-// Thread part T(t) of a layout index: XOR of tab[i] over the set bits i of the
-// thread id.  The all-ones / all-zero mask of every thread bit is formed once
-// per thread, so that T(t) is one AND-XOR per bit with no branches (the tables
-// hold 0 for bits at or above the tile's thread bits).
+// log2 of the threads of a workgroup (a tile with fewer thread bits leaves lanes idle)
 template <int NT>
-struct ThreadBits {
-  static constexpr int B = NT <= 64 ? 6 : NT <= 128 ? 7 : 8;
-  uint32_t m[B];
-  __device__ __forceinline__ explicit ThreadBits(int t) {
-#pragma unroll
-    for (int i = 0; i < B; ++i) m[i] = 0u - (((uint32_t)t >> i) & 1u);
-  }
-  __device__ __forceinline__ uint32_t operator()(const uint32_t* tab) const {
-    uint32_t v = 0;
-#pragma unroll
-    for (int i = 0; i < B; ++i) v ^= m[i] & cld(tab + i);
-    return v;
-  }
+struct ThreadBitsOf {
+  static constexpr int value = NT <= 64 ? 6 : NT <= 128 ? 7 : 8;
 };
 
 // Per-register-bit contributions of a layout, loaded once per op (uniform).
@@ -191,46 +177,64 @@ __device__ __forceinline__ void flip_signs(float2 (&a)[NA], uint32_t sign) {
   }
 }
 
-// Butterfly reduce-scatter of 16 per-lane values over a wave of 64 lanes.
-// Afterwards lane L holds the wave sum of value ((L >> 2) & 15).
+// Cross-lane moves of one float (DPP, no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+constexpr int kDppQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]: lane ^ 1
+constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]: lane ^ 2
+constexpr int kDppRowRor4 = 0x124;   // row_ror:4 (rows of 16 lanes)
+constexpr int kDppRowRor8 = 0x128;   // row_ror:8: lane ^ 8 inside a row
+
+// x (lanes whose bit is clear) or y (lanes whose bit is set), each summed with
+// the same value of the partner lane across that bit
+__device__ __forceinline__ float sum_split(float x, float y, float xp, float yp, bool hi) {
+  return hi ? y + yp : x + xp;
+}
+
+// Reduce-scatter of 16 per-lane values over a wave of 64 lanes.  Afterwards
+// every lane holds the wave sum of value wave_sum_index(lane).  Lane bits 5 and
+// 4 are folded with v_permlane32_swap / v_permlane16_swap (one swap and one add
+// per pair of values), bits 0 and 1 with quad DPP moves, and the last value is
+// summed over bits 3 and 2 with row rotations; no LDS instruction is issued.
 __device__ __forceinline__ float wave_reduce16(float (&v)[16], int lane) {
-  {
-    const bool hi = (lane & 32) != 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const float send = hi ? v[i] : v[i + 8];
-      const float keep = hi ? v[i + 8] : v[i];
-      v[i] = keep + __shfl_xor(send, 32);
-    }
+  for (int i = 0; i < 8; ++i) {
+    // the upper half of v[i] and the lower half of v[i + 8] change places: the
+    // lower lanes then hold both halves of v[i], the upper lanes both of v[i + 8]
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 8]), false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
-  {
-    const bool hi = (lane & 16) != 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float send = hi ? v[i] : v[i + 4];
-      const float keep = hi ? v[i + 4] : v[i];
-      v[i] = keep + __shfl_xor(send, 16);
-    }
+  for (int i = 0; i < 4; ++i) {
+    // odd rows of v[i] with even rows of v[i + 4]
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 4]), false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
   {
-    const bool hi = (lane & 8) != 0;
+    const bool hi = (lane & 1) != 0;
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const float send = hi ? v[i] : v[i + 2];
-      const float keep = hi ? v[i + 2] : v[i];
-      v[i] = keep + __shfl_xor(send, 8);
-    }
+    for (int i = 0; i < 2; ++i)
+      v[i] = sum_split(v[i], v[i + 2], dpp_mov<kDppQuadXor1>(v[i]), dpp_mov<kDppQuadXor1>(v[i + 2]), hi);
   }
   {
-    const bool hi = (lane & 4) != 0;
-    const float send = hi ? v[0] : v[1];
-    const float keep = hi ? v[1] : v[0];
-    v[0] = keep + __shfl_xor(send, 4);
+    const bool hi = (lane & 2) != 0;
+    v[0] = sum_split(v[0], v[1], dpp_mov<kDppQuadXor2>(v[0]), dpp_mov<kDppQuadXor2>(v[1]), hi);
   }
-  v[0] += __shfl_xor(v[0], 2);
-  v[0] += __shfl_xor(v[0], 1);
+  // full sums over lane bits 3 and 2: lane ^ 8 inside a row; then a rotation by 4,
+  // which reaches lane ^ 4 once the values no longer depend on bit 3
+  v[0] += dpp_mov<kDppRowRor8>(v[0]);
+  v[0] += dpp_mov<kDppRowRor4>(v[0]);
   return v[0];
 }
+
+// Index of the value whose wave sum lane `lane` holds after wave_reduce16; the
+// lanes with bits 2 and 3 clear hold each index once.
+__device__ __forceinline__ int wave_sum_index(int lane) {
+  return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + (lane & 1) * 2 + ((lane >> 1) & 1);
+}
+__device__ __forceinline__ bool wave_sum_writer(int lane) { return (lane & 12) == 0; }
 
 __device__ __forceinline__ const float* run_coef(const KArgs& A, int ref, int sample) {
   return ref >= 0 ? A.coef_sh + 8 * (size_t)ref : A.coef_ps + 8 * ((size_t)sample * A.n_ps + (-1 - ref));
@@ -286,21 +290,34 @@ struct PassCtx {
   static constexpr int WAVES = NT / 64;
   KArgs A;
   float2* lds;
-  ThreadBits<NT> tbase;
+  int t;
   uint32_t tlog;
   bool active;
   int sample, lane, wave, n_slots;
 
-  // op bodies, shared by the single ops and the fused epoch op
-  __device__ __forceinline__ void perm(float2 (&a)[NA], float2 (&l)[NA], float2& ph, int from, int to) const {
+  // The thread's {LDS offset, logical index} bases of a layout, read from the
+  // plan's per-thread table (a vector load through the caches).
+  __device__ __forceinline__ uint2 base2(int layout) const {
+    return *reinterpret_cast<const uint2*>(A.tbases + ((size_t)layout * NT + t));
+  }
+  __device__ __forceinline__ uint32_t mem_base(int layout) const {
+    return A.tbases[(size_t)layout * NT + t].mem;
+  }
+  // logical base of `layout`, reusing the bases `cur` of layout `cur_idx` when they match
+  __device__ __forceinline__ uint32_t log_base(int layout, int cur_idx, uint2 cur) const {
+    return tlog | (layout == cur_idx ? cur.y : base2(layout).y);
+  }
+
+  // op bodies, shared by the single ops and the fused epoch op.  bf, bt: the
+  // thread's LDS bases of the layouts before and after the exchange.
+  __device__ __forceinline__ void perm(float2 (&a)[NA], float2 (&l)[NA], float2& ph, int from, int to,
+                                       uint32_t bf, uint32_t bt) const {
   // flush the pending phase (an exact identity when none is pending)
   scale_all<NA>(a, ph);
   if constexpr (BWD) scale_all<NA>(l, ph);
   ph = make_float2(1.f, 0.f);
   const LayoutRec* F = A.layouts + from;
   const LayoutRec* T = A.layouts + to;
-  const uint32_t bf = tbase(F->lds_thr);
-  const uint32_t bt = tbase(T->lds_thr);
   RegBits<R> rf, rt;
   rf.load(F->lds_reg);
   rt.load(T->lds_reg);
@@ -359,9 +376,8 @@ struct PassCtx {
   if constexpr (BWD) apply_ry_all<R>(l, tt, sn);
   }
 
-  __device__ __forceinline__ void diagt(float2 (&a)[NA], float2 (&l)[NA], float2& ph, int layout, int czg0, int nczg, int pev0, int npev) const {
-  const LayoutRec* L = A.layouts + layout;
-  const uint32_t x = tlog | tbase(L->log_thr);
+  // x: the thread's logical base index in the current layout
+  __device__ __forceinline__ void diagt(float2 (&a)[NA], float2 (&l)[NA], float2& ph, uint32_t x, int czg0, int nczg, int pev0, int npev) const {
   uint32_t par = 0;
   for (int i = 0; i < nczg; ++i) {
     const CzGroup g = ld_czg(A.czg + czg0 + i);
@@ -396,10 +412,8 @@ struct PassCtx {
   }
   }
 
-  __device__ __forceinline__ void cza(float2 (&a)[NA], float2 (&l)[NA], float2& ph, int cza, int layout) const {
+  __device__ __forceinline__ void cza(float2 (&a)[NA], float2 (&l)[NA], float2& ph, int cza, uint32_t x) const {
   const CzaRec* C = A.cza + cza;
-  const LayoutRec* L = A.layouts + layout;
-  const uint32_t x = tlog | tbase(L->log_thr);
   uint32_t sign = cld(&C->sr);
 #pragma unroll
   for (int j = 0; j < R; ++j)
@@ -436,14 +450,15 @@ struct PassCtx {
 #pragma unroll
       for (int i = 0; i < 16; ++i) v[i] = 0.f;
       func3_all<R>(a, l, v);
-      // lanes beyond a small tile hold copies of in-tile elements: no share
-      if (!active) {
+      // lanes beyond a small tile hold copies of in-tile elements: no share (a
+      // uniform test first, so that full tiles skip the per-lane selects)
+      if (A.tb < ThreadBitsOf<NT>::value && !active) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = 0.f;
       }
       const float sum = wave_reduce16(v, lane);
-      const int idx = (lane >> 2) & 15;
-      if ((lane & 3) == 0 && idx < 3 * R) {
+      const int idx = wave_sum_index(lane);
+      if (wave_sum_writer(lane) && idx < 3 * R) {
         const int e = idx / 3, pq = idx - 3 * e;
         int slot = sl[0];
 #pragma unroll
@@ -469,7 +484,6 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
   const int wave = t >> 6;
   const int tb = A.tb;
   const bool active = t < (1 << tb);
-  const ThreadBits<NT> tbase(t);
   const int sl = item >> A.tiles_log2;
   const int tile = item & ((1 << A.tiles_log2) - 1);
   const int sample = A.sample0 + sl;
@@ -496,7 +510,10 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
   // multiplies psi (and, in the backward, lambda as well)
   float2 ph = make_float2(1.f, 0.f);
 
-  const PassCtx<R, NT, BWD> cx{A, lds, tbase, tlog, active, sample, lane, wave, n_slots};
+  const PassCtx<R, NT, BWD> cx{A, lds, t, tlog, active, sample, lane, wave, n_slots};
+  // bases of the layout the tile is in (cur_idx: its index, -1 = not loaded)
+  int cur_idx = -1;
+  uint2 cur = make_uint2(0u, 0u);
 
   // the next op record is fetched while the current one executes
   Op next = ld_op(A.ops);
@@ -506,7 +523,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
     switch (op.kind) {
       case OP_INIT0: {
         const LayoutRec* L = A.layouts + op.a;
-        const uint32_t base = tlog | tbase(L->log_thr);
+        const uint32_t base = cx.log_base(op.a, cur_idx, cur);
         RegBits<R> rb;
         rb.load(L->log_reg);
 #pragma unroll
@@ -516,7 +533,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
       }
       case OP_LOAD: {
         const LayoutRec* L = A.layouts + op.a;
-        const uint32_t base = (op.c ? tout : tin) | tbase(L->mem_thr);
+        const uint32_t base = (op.c ? tout : tin) | cx.mem_base(op.a);
         RegBits<R> rb;
         rb.load(L->mem_reg);
         // every lane loads: the thread tables are zero above the tile's thread
@@ -543,7 +560,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         if constexpr (BWD) scale_all<NA>(l, ph);
         ph = make_float2(1.f, 0.f);
         const LayoutRec* L = A.layouts + op.a;
-        const uint32_t base = (op.c ? tout : tin) | tbase(L->mem_thr);
+        const uint32_t base = (op.c ? tout : tin) | cx.mem_base(op.a);
         RegBits<R> rb;
         rb.load(L->mem_reg);
         if (active && A.dst) {
@@ -574,9 +591,13 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         }
         break;
       }
-      case OP_PERM:
-        cx.perm(a, l, ph, op.a, op.b);
+      case OP_PERM: {
+        const uint32_t bf = op.a == cur_idx ? cur.x : cx.base2(op.a).x;
+        cur = cx.base2(op.b);
+        cur_idx = op.b;
+        cx.perm(a, l, ph, op.a, op.b, bf, cur.x);
         break;
+      }
       case OP_RY:
         cx.ry(a, l, ph, op.a, op.b);
         break;
@@ -584,10 +605,10 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         cx.ryg(a, l, ph, op.b, op.c);
         break;
       case OP_DIAGT:
-        cx.diagt(a, l, ph, op.a, op.b, op.c, op.d, op.e);
+        cx.diagt(a, l, ph, cx.log_base(op.a, cur_idx, cur), op.b, op.c, op.d, op.e);
         break;
       case OP_CZA:
-        cx.cza(a, l, ph, op.a, op.b);
+        cx.cza(a, l, ph, op.a, cx.log_base(op.b, cur_idx, cur));
         break;
       case OP_PHASEA:
         cx.phasea(a, l, ph, op.a, op.b);
@@ -604,23 +625,40 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
           const int cza = cld(&E->cza), cza_layout = cld(&E->cza_layout);
           const int ry_first = cld(&E->ry_a), ry_mask = cld(&E->ry_b);
           if constexpr (!BWD) {
-            cx.perm(a, l, ph, perm_from, perm_to);
+            // bases before the PERM: carried from the previous epoch (the planner chains
+            // the layouts; the load is a fallback), requested before those after it so
+            // that the LDS writes wait for the first load only
+            uint32_t bf = cur.x;
+            if (perm_from != cur_idx) bf = cx.base2(perm_from).x;
+            const uint2 nb = cx.base2(perm_to);
+            cx.perm(a, l, ph, perm_from, perm_to, bf, nb.x);
+            cur = nb;
+            cur_idx = perm_to;
             if (diag_layout >= 0)
-              cx.diagt(a, l, ph, diag_layout, cld(&E->czg_first), cld(&E->czg_count), cld(&E->pev_first),
-                       cld(&E->pev_count));
+              cx.diagt(a, l, ph, cx.log_base(diag_layout, cur_idx, cur), cld(&E->czg_first), cld(&E->czg_count),
+                       cld(&E->pev_first), cld(&E->pev_count));
             for (int p = pha0; p < pha0 + n_pha; ++p) cx.phasea(a, l, ph, cld(&A.phas[p].regbit), cld(&A.phas[p].pev));
-            if (cza >= 0) cx.cza(a, l, ph, cza, cza_layout);
+            if (cza >= 0) cx.cza(a, l, ph, cza, cx.log_base(cza_layout, cur_idx, cur));
             cx.ryg(a, l, ph, ry_first, ry_mask);
           } else {
+            // the tile is in layout perm_from until the PERM that ends the epoch
+            if (perm_from != cur_idx) {
+              cur = cx.base2(perm_from);
+              cur_idx = perm_from;
+            }
+            // bases after the PERM, requested now: the epoch's work hides the load
+            const uint2 nb = cx.base2(perm_to);
             const int n_func = cld(&E->func_count);
             if (n_func > 0) cx.func(a, l, ph, n_func, cld(&E->func_first), 0);
             cx.ryg(a, l, ph, ry_first, ry_mask);
-            if (cza >= 0) cx.cza(a, l, ph, cza, cza_layout);
+            if (cza >= 0) cx.cza(a, l, ph, cza, cx.log_base(cza_layout, cur_idx, cur));
             for (int p = pha0; p < pha0 + n_pha; ++p) cx.phasea(a, l, ph, cld(&A.phas[p].regbit), cld(&A.phas[p].pev));
             if (diag_layout >= 0)
-              cx.diagt(a, l, ph, diag_layout, cld(&E->czg_first), cld(&E->czg_count), cld(&E->pev_first),
-                       cld(&E->pev_count));
-            cx.perm(a, l, ph, perm_from, perm_to);
+              cx.diagt(a, l, ph, cx.log_base(diag_layout, cur_idx, cur), cld(&E->czg_first), cld(&E->czg_count),
+                       cld(&E->pev_first), cld(&E->pev_count));
+            cx.perm(a, l, ph, perm_from, perm_to, cur.x, nb.x);
+            cur = nb;
+            cur_idx = perm_to;
           }
         }
         break;
@@ -629,7 +667,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
         if constexpr (!BWD) {
           if (!A.do_expect) break;
           const LayoutRec* L = A.layouts + op.a;
-          const uint32_t base = tlog | tbase(L->log_thr);
+          const uint32_t base = cx.log_base(op.a, cur_idx, cur);
           RegBits<R> rb;
           rb.load(L->log_reg);
           for (int k0 = 0; k0 < A.K; k0 += 16) {
@@ -646,8 +684,8 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
                 if (k0 + k < A.K) v[k] += (__popc(x & cld(A.zmask + k0 + k)) & 1) ? -p : p;
             }
             const float s = wave_reduce16(v, lane);
-            const int idx = (lane >> 2) & 15;
-            if ((lane & 3) == 0 && k0 + idx < A.K)
+            const int idx = wave_sum_index(lane);
+            if (wave_sum_writer(lane) && k0 + idx < A.K)
               A.partE[((size_t)item * WAVES + wave) * A.K + k0 + idx] = s;
           }
         }
@@ -656,7 +694,7 @@ __device__ __forceinline__ void pass_body(const KArgs& A, const int item) {
       case OP_SEED: {
         if constexpr (BWD) {
           const LayoutRec* L = A.layouts + op.a;
-          const uint32_t base = tlog | tbase(L->log_thr);
+          const uint32_t base = cx.log_base(op.a, cur_idx, cur);
           RegBits<R> rb;
           rb.load(L->log_reg);
           const float* g = A.dE + (size_t)sample * A.K;

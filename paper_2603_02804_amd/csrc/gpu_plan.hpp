@@ -26,6 +26,30 @@ inline void push_table(std::vector<char>& blob, std::vector<size_t>& offs, const
   offs.push_back(off);
 }
 
+// Per-thread bases of every layout, so that the pass kernels read a thread's
+// part of an index instead of forming it with one AND-XOR per thread bit: entry
+// [layout * NT + t] = {LDS byte offset, logical basis index, memory index} of
+// thread t, the XOR of lds_thr[i] (log_thr[i], mem_thr[i]) over the set bits i of t.
+inline std::vector<ThrBase> thread_base_table(const Schedule& S) {
+  std::vector<ThrBase> tab;
+  if (S.NT <= 0) return tab;
+  tab.resize(S.layouts.size() * (size_t)S.NT);
+  for (size_t l = 0; l < S.layouts.size(); ++l) {
+    const LayoutRec& L = S.layouts[l];
+    for (int t = 0; t < S.NT; ++t) {
+      ThrBase b{0u, 0u, 0u, 0u};
+      for (int i = 0; i < kMaxThreadBits; ++i)
+        if ((t >> i) & 1) {
+          b.lds ^= L.lds_thr[i];
+          b.log ^= L.log_thr[i];
+          b.mem ^= L.mem_thr[i];
+        }
+      tab[l * (size_t)S.NT + t] = b;
+    }
+  }
+  return tab;
+}
+
 inline qf_status upload_plan(const PlanCore& c, DevPlan* d, std::string* msg) {
   std::vector<char> blob;
   std::vector<size_t> o;
@@ -59,6 +83,7 @@ inline qf_status upload_plan(const PlanCore& c, DevPlan* d, std::string* msg) {
   push_table(blob, o, c.S.phas);         // 25
   push_table(blob, o, pauli_table(c));   // 26
   push_table(blob, o, c.C.consts);       // 27
+  push_table(blob, o, thread_base_table(c.S));   // 28
   d->bytes = blob.size();
   if (hipMalloc(&d->blob, d->bytes) != hipSuccess) {
     if (msg) *msg = "hipMalloc of plan tables failed";
@@ -100,6 +125,7 @@ inline qf_status upload_plan(const PlanCore& c, DevPlan* d, std::string* msg) {
   p.phas = (const PhaEntry*)(b + o[25]);
   p.pauli = (const PauliRec*)(b + o[26]);
   t.consts = (const double*)(b + o[27]);
+  p.tbases = (const ThrBase*)(b + o[28]);
   return QF_OK;
 }
 

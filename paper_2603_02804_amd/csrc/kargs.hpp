@@ -44,6 +44,7 @@ struct PlanPtrs {
   const PhaseEv* pev = nullptr;
   const CzaRec* cza = nullptr;
   const PauliRec* pauli = nullptr;   // observables in the final state's bit order
+  const ThrBase* tbases = nullptr;   // [layout][thread] bases (S.NT threads per layout)
   Tabs tabs{};
 };
 
@@ -51,6 +52,7 @@ struct PlanPtrs {
 struct KArgs {
   const Op* ops;
   const LayoutRec* layouts;
+  const ThrBase* tbases;      // [layout][NT] thread bases of every layout
   const CzGroup* czg;
   const FuncEntry* funcs;
   const RygEntry* rygs;
@@ -111,6 +113,7 @@ inline KArgs make_pass_args(const PlanCore& c, const PlanPtrs& d, const CoefPtrs
   A.ops = d.ops + (L.bwd ? pr.bop_begin : (L.load_input ? pr.fload_begin : pr.fop_begin));
   A.n_ops = L.bwd ? pr.bop_count : pr.fop_count;
   A.layouts = d.layouts;
+  A.tbases = d.tbases;
   A.czg = d.czg;
   A.funcs = d.funcs;
   A.rygs = d.rygs;

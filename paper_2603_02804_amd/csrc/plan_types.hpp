@@ -107,6 +107,12 @@ struct LayoutRec {
   int32_t pad[1];
 };
 
+// Thread part of a layout's three indices for one thread: the XOR of lds_thr,
+// log_thr and mem_thr over the set bits of the thread id.
+struct ThrBase {
+  uint32_t lds, log, mem, pad;
+};
+
 // XOR of per-bit contributions over the set bits of jj.
 inline uint32_t reg_index(const uint32_t* per_bit, int jj) {
   uint32_t v = 0;
