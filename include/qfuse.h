@@ -219,6 +219,23 @@ qf_status qf_forward(qf_plan* plan, const float* theta, const float* x, float* E
                      void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): qf_forward with the
+ * workspace taken from a library-owned device array of QF_NOALLOC_SCRATCH_BYTES
+ * (64 MiB), one per GPU, held from module load until the process ends.  Same
+ * arguments, kernels and results as qf_forward (bit for bit); the call allocates
+ * nothing and records no profiling events.  Every call on a GPU shares that GPU's
+ * array and leaves its contents there, so calls that overlap on one GPU (several
+ * streams or host threads) race and must be ordered by the caller; no
+ * qf_backward can follow this call (its checkpoints live in the shared array).
+ * Errors: those of qf_forward, QF_ERR_WORKSPACE when qf_workspace_size of the
+ * plan exceeds QF_NOALLOC_SCRATCH_BYTES (use qf_forward), QF_ERR_DEVICE when the
+ * array's device address cannot be obtained.
+ */
+#define QF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+qf_status qf_forward_noalloc(qf_plan* plan, const float* theta, const float* x, float* E, void* stream);
+
+/*
  * Backward pass by the adjoint method (Sec. 2.2): the adjoint state is seeded as
  * lambda_M = 2 sum_k dE_k O_k psi_M (eq. bwd_exp_val with the chain rule), each
  * angle's gradient is Re<lambda_j| dU_j/dphi |psi_{j-1}> (eq. grad_theta) and

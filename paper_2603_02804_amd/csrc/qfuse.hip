@@ -518,8 +518,41 @@ struct GpuExec {
 // ---------------------------------------------------------------------------
 using namespace qf;
 
+// Workspace of qf_forward_noalloc.  Every GPU the library runs on holds its own
+// copy of this array from module load until the process ends.  In host code the
+// name stands for a host-side shadow, not a device address: the device address is
+// taken once per device with hipGetSymbolAddress and only that pointer is used.
+static __device__ __align__(256) unsigned char scratch[QF_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 thread_local std::string g_last_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first call
+// per device, with that device current).
+bool noalloc_scratch(void** out, std::string* msg) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    *msg = "qf_forward_noalloc: no usable current HIP device";
+    return false;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      *msg = std::string("qf_forward_noalloc: hipGetSymbolAddress of the scratch array failed: ") +
+             hipGetErrorString(e);
+      return false;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return true;
+}
 
 qf_status fail(qf_status s, const std::string& m) {
   g_last_error = m;
@@ -764,6 +797,28 @@ qf_status qf_forward_psi0(qf_plan* p, const float* theta, const float* x, const 
 qf_status qf_forward(qf_plan* p, const float* theta, const float* x, float* E, void* ws, size_t ws_bytes,
                      void* stream) {
   return qf_forward_psi0(p, theta, x, nullptr, E, ws, ws_bytes, stream);
+}
+
+qf_status qf_forward_noalloc(qf_plan* p, const float* theta, const float* x, float* E, void* stream) {
+  if (!p) return fail(QF_ERR_INVALID_ARG, "plan is NULL");
+  if (p->core.ws_bytes > QF_NOALLOC_SCRATCH_BYTES)
+    return fail(QF_ERR_WORKSPACE, "qf_forward_noalloc: the plan needs a workspace of " +
+                                      std::to_string(p->core.ws_bytes) + " bytes, more than the " +
+                                      std::to_string((size_t)QF_NOALLOC_SCRATCH_BYTES) +
+                                      "-byte library array; use qf_forward with a caller workspace");
+  void* ws = nullptr;
+  std::string msg;
+  if (!noalloc_scratch(&ws, &msg)) return fail(QF_ERR_DEVICE, msg);
+  qf_status st = check_call(p, ws, QF_NOALLOC_SCRATCH_BYTES);
+  if (st != QF_OK) return st;
+  const PlanCore& c = p->core;
+  if (c.c128) return fail(QF_ERR_INVALID_ARG, "complex128 plan: call qf_forward_c128");
+  if (!E || (c.C.P > 0 && !theta) || (c.C.F > 0 && !x)) return fail(QF_ERR_INVALID_ARG, "NULL buffer");
+  // no profiling events on this path: it creates nothing
+  GpuExec ex(c, p->dev, (hipStream_t)stream);
+  st = run_forward(c, ex, theta, x, E, (char*)ws, nullptr);
+  if (st != QF_OK) return fail(st, ex.msg);
+  return QF_OK;
 }
 
 qf_status qf_backward_psi0(qf_plan* p, const float* theta, const float* x, const float* psi0, const float* dE,

@@ -96,6 +96,7 @@ def library() -> ctypes.CDLL:
             "qf_plan_create": [P, I32, P, P], "qf_plan_destroy": [P], "qf_plan_get_info": [P, P],
             "qf_workspace_size": [P, P],
             "qf_forward": [P, P, P, P, P, SZ, P],
+            "qf_forward_noalloc": [P, P, P, P, P],
             "qf_backward": [P, P, P, P, P, P, P, SZ, P],
             "qf_forward_psi0": [P, P, P, P, P, P, SZ, P],
             "qf_backward_psi0": [P, P, P, P, P, P, P, P, SZ, P],
@@ -163,6 +164,10 @@ def qf_workspace_size(plan) -> int:
 def qf_forward(plan, theta: torch.Tensor, x: Optional[torch.Tensor], E: torch.Tensor, ws: torch.Tensor,
                ws_bytes: int, stream) -> None:
     _check(library().qf_forward(plan, _ptr(theta), _ptr(x), _ptr(E), _ptr(ws), ws_bytes, stream))
+
+
+def qf_forward_noalloc(plan, theta: torch.Tensor, x: Optional[torch.Tensor], E: torch.Tensor, stream) -> None:
+    _check(library().qf_forward_noalloc(plan, _ptr(theta), _ptr(x), _ptr(E), stream))
 
 
 def qf_backward(plan, theta: torch.Tensor, x: Optional[torch.Tensor], dE: torch.Tensor, dtheta: torch.Tensor,
@@ -287,6 +292,21 @@ class Plan:
             qf_forward_c128(self.handle, theta, x, p0, E, ws, ws.numel(), s)
         else:
             qf_forward_psi0(self.handle, theta, x, p0, E, ws, ws.numel(), s)
+        return E
+
+    def forward_noalloc(self, theta: torch.Tensor, x: Optional[torch.Tensor],
+                        E: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """qf_forward_noalloc: the forward with the library's own device array as workspace
+        (no backward can follow; calls on one GPU must not overlap)."""
+        self._check_inputs(theta, x)
+        if self.c128:
+            raise ValueError("qf_forward_noalloc takes float32 plans only")
+        theta = theta.contiguous()
+        x = x.contiguous() if x is not None else None
+        if E is None:
+            E = torch.empty(self.batch, self.circuit.n_obs, dtype=self.dtype, device=theta.device)
+        s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        qf_forward_noalloc(self.handle, theta, x, E, s)
         return E
 
     def backward(self, theta: torch.Tensor, x: Optional[torch.Tensor], dE: torch.Tensor, ws: torch.Tensor,

@@ -109,6 +109,7 @@ def test_null_arguments(lib):
     assert lib.qf_circuit_create(None, ctypes.byref(h)) == INVALID
     assert lib.qf_plan_create(None, 1, None, ctypes.byref(h)) == INVALID
     assert lib.qf_forward(None, None, None, None, None, 0, None) == INVALID
+    assert lib.qf_forward_noalloc(None, None, None, None, None) == INVALID
     assert lib.qf_backward(None, None, None, None, None, None, None, 0, None) == INVALID
     assert lib.qf_forward_psi0(None, None, None, None, None, None, 0, None) == INVALID
     assert lib.qf_backward_psi0(None, None, None, None, None, None, None, None, 0, None) == INVALID
