@@ -456,7 +456,8 @@ def bench_sweep(args, dev) -> int:
             del ws
             return sec
 
-        plan = qfuse.Plan(circ, B, qfuse.make_tuning(uncompute=1))
+        # the whole batch in one micro-batch: a one-layer circuit has two passes, each a short launch
+        plan = qfuse.Plan(circ, B, qfuse.make_tuning(uncompute=1, micro_batch=B))
         info = plan.info
         sec = timed(plan, B, max(1, args.steps))
         # algorithmic bytes of the call: the plan's passes plus the initial-state read

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_small_multi(const SmallJob* j
       a.Gr = rebase(a.Gr, ws);
       a.dtheta = P.dtheta;
       a.dx = P.dx;
-      reduce_grads_body(a, idx);
+      reduce_grads_body(a, blk, (int)threadIdx.x, fsum);
       break;
     }
     default:
@@ -182,19 +182,41 @@ static qf_status upload_program(const Program& P, DevProgram* d, std::string* ms
   return QF_OK;
 }
 
+// Streams and events that let the groups of a program run concurrently: group 0
+// runs on the caller's stream, group g > 0 on side[g - 1], forked from and joined
+// back into the caller's stream (also inside a graph capture, where the fork
+// and join become graph dependencies).
+struct GroupStreams {
+  std::vector<hipStream_t> side;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+};
+
 static hipError_t launch_program(const Program& P, const DevProgram& d, char* ws, const CircPtrs* ptrs,
-                                 hipStream_t st) {
+                                 hipStream_t st, const GroupStreams& gs) {
+  const int G = P.groups;
+  if (G > 1 && (int)gs.side.size() < G - 1) return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
+  if (G > 1) {
+    if ((e = hipEventRecord(gs.fork, st)) != hipSuccess) return e;
+    for (int g = 1; g < G; ++g)
+      if ((e = hipStreamWaitEvent(gs.side[g - 1], gs.fork, 0)) != hipSuccess) return e;
+  }
   for (const MergedLaunch& L : P.launches) {
+    hipStream_t s = L.group == 0 ? st : gs.side[L.group - 1];
     if (L.cls >= 0) {
       MultiPassFn fn = select_multi(L.cls);
-      hipLaunchKernelGGL(fn, dim3(L.blocks), dim3(class_NT(L.cls)), L.shmem, st, d.pjobs + L.job0,
+      hipLaunchKernelGGL(fn, dim3(L.blocks), dim3(class_NT(L.cls)), L.shmem, s, d.pjobs + L.job0,
                          d.pstart + L.job0, L.n_jobs, ws, ptrs);
     } else {
-      hipLaunchKernelGGL(k_small_multi, dim3(L.blocks), dim3(kSmallThreads), L.shmem, st, d.sjobs + L.job0,
+      hipLaunchKernelGGL(k_small_multi, dim3(L.blocks), dim3(kSmallThreads), L.shmem, s, d.sjobs + L.job0,
                          d.sstart + L.job0, L.n_jobs, ws, ptrs);
     }
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  for (int g = 1; g < G; ++g) {
+    if ((e = hipEventRecord(gs.join[g - 1], gs.side[g - 1])) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(st, gs.join[g - 1], 0)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -222,6 +244,7 @@ struct qf_batch {
   size_t ws_bytes = 0;
   Direction dir[2];                  // 0 forward, 1 backward
   hipStream_t capture = nullptr;     // private stream for graph capture only
+  GroupStreams gs;                   // side streams of the concurrent groups
   int mode = QF_LAUNCH_GRAPH;
   int device = 0;
   qf_batch_info info{};
@@ -237,6 +260,9 @@ static void destroy_batch(qf_batch* b) {
     if (d.dev.blob) (void)hipFree(d.dev.blob);
   }
   if (b->capture) (void)hipStreamDestroy(b->capture);
+  for (hipStream_t s : b->gs.side) (void)hipStreamDestroy(s);
+  for (hipEvent_t e : b->gs.join) (void)hipEventDestroy(e);
+  if (b->gs.fork) (void)hipEventDestroy(b->gs.fork);
   for (qf_plan* p : b->plans) qf_plan_destroy(p);
   delete b;
 }
@@ -301,8 +327,8 @@ qf_status qf_batch_create(const qf_circuit* const* circuits, const int32_t* samp
       st = QF_ERR_INTERNAL;
     }
     const std::vector<int> order = batch_order(cores);
-    if (st == QF_OK && (!merge_programs(fwd, order, &b->dir[0].prog, &msg) ||
-                        !merge_programs(bwd, order, &b->dir[1].prog, &msg)))
+    if (st == QF_OK && (!merge_grouped(fwd, cores, order, &b->dir[0].prog, &msg) ||
+                        !merge_grouped(bwd, cores, order, &b->dir[1].prog, &msg)))
       st = QF_ERR_UNSUPPORTED;
     for (int k = 0; st == QF_OK && k < 2; ++k)
       for (const MergedLaunch& L : b->dir[k].prog.launches)
@@ -329,6 +355,26 @@ qf_status qf_batch_create(const qf_circuit* const* circuits, const int32_t* samp
   if (st == QF_OK && hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess) {
     st = QF_ERR_DEVICE;
     msg = "hipStreamCreateWithFlags failed";
+  }
+  // one side stream (default priority) and join event per group after the first
+  const int groups = std::max(b->dir[0].prog.groups, b->dir[1].prog.groups);
+  if (st == QF_OK && groups > 1) {
+    if (hipEventCreateWithFlags(&b->gs.fork, hipEventDisableTiming) != hipSuccess) st = QF_ERR_DEVICE;
+    for (int g = 1; st == QF_OK && g < groups; ++g) {
+      hipStream_t s = nullptr;
+      hipEvent_t e = nullptr;
+      if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+        st = QF_ERR_DEVICE;
+        break;
+      }
+      b->gs.side.push_back(s);
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        st = QF_ERR_DEVICE;
+        break;
+      }
+      b->gs.join.push_back(e);
+    }
+    if (st != QF_OK) msg = "creation of the group streams failed";
   }
   if (st != QF_OK) {
     destroy_batch(b);
@@ -412,7 +458,7 @@ qf_status stage_pointers(qf_batch* b, int k, const std::vector<CircPtrs>& tab, h
 qf_status run_merged(qf_batch* b, int k, char* ws, hipStream_t st) {
   Direction& d = b->dir[k];
   if (b->mode == QF_LAUNCH_MERGED) {
-    const hipError_t e = launch_program(d.prog, d.dev, ws, d.d_ptrs, st);
+    const hipError_t e = launch_program(d.prog, d.dev, ws, d.d_ptrs, st, b->gs);
     if (e != hipSuccess) return set_error(QF_ERR_DEVICE, std::string("merged launch: ") + hipGetErrorString(e));
     return QF_OK;
   }
@@ -424,7 +470,7 @@ qf_status run_merged(qf_batch* b, int k, char* ws, hipStream_t st) {
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return set_error(QF_ERR_DEVICE, "hipStreamBeginCapture failed");
-    const hipError_t e = launch_program(d.prog, d.dev, ws, d.d_ptrs, b->capture);
+    const hipError_t e = launch_program(d.prog, d.dev, ws, d.d_ptrs, b->capture, b->gs);
     const hipError_t e2 = hipStreamEndCapture(b->capture, &g);
     if (e != hipSuccess || e2 != hipSuccess || !g) {
       if (g) (void)hipGraphDestroy(g);

@@ -124,8 +124,7 @@ struct RecordExec {
   void reduce_grads(int nb, int sample0, const float* Gr, float*, float*, bool accumulate) {
     SmallJob j = job(SJ_REDUCE_G, circ);
     j.u.rg = make_reduce_grads_args<float>(c, d, nb, sample0, Gr, nullptr, nullptr, accumulate);
-    const long long n = reduce_grads_items(j.u.rg);
-    if (n > 0) small(j, blocks_for(n), 0);
+    if (j.u.rg.P > 0 || j.u.rg.dx_items() > 0) small(j, reduce_grads_blocks(j.u.rg), reduce_grads_shmem());
   }
 };
 
@@ -135,6 +134,7 @@ struct MergedLaunch {
   int32_t n_jobs;
   uint32_t blocks;
   uint32_t shmem;
+  int group = 0;      // circuits of one tile shape: groups run on streams of their own
 };
 
 struct Program {
@@ -146,6 +146,7 @@ struct Program {
   std::vector<int32_t> sstart;
   int steps = 0;
   int64_t jobs = 0;                 // launches of the circuits one by one
+  int groups = 1;                   // independent launch sequences (one per tile shape)
 };
 
 // Merges the circuits' sequences; within a launch, jobs follow `order`.
@@ -204,6 +205,52 @@ inline bool merge_programs(const std::vector<CircProgram>& cps, const std::vecto
       P->jobs += L.n_jobs;
       P->launches.push_back(L);
     }
+  }
+  return true;
+}
+
+// Circuits grouped by tile shape (the pass kernel variant their plan uses), each
+// group merged on its own: the groups share no launch, so the caller can run
+// them concurrently.  Groups are ordered by work, heaviest first; `order` keeps
+// its order inside each group.  The job tables of all groups are concatenated.
+inline bool merge_grouped(const std::vector<CircProgram>& cps, const std::vector<const PlanCore*>& cores,
+                          const std::vector<int>& order, Program* P, std::string* msg) {
+  std::vector<int> keys;
+  std::vector<std::vector<int>> members;
+  std::vector<double> weight;
+  for (int c : order) {
+    const int key = pass_class(cores[c]->S.R, cores[c]->S.NT, false);
+    size_t g = 0;
+    while (g < keys.size() && keys[g] != key) ++g;
+    if (g == keys.size()) {
+      keys.push_back(key);
+      members.emplace_back();
+      weight.push_back(0.0);
+    }
+    members[g].push_back(c);
+    weight[g] += (double)cores[c]->amps * cores[c]->P * cores[c]->B;
+  }
+  std::vector<size_t> gorder(keys.size());
+  for (size_t g = 0; g < gorder.size(); ++g) gorder[g] = g;
+  std::stable_sort(gorder.begin(), gorder.end(), [&](size_t a, size_t b) { return weight[a] > weight[b]; });
+  *P = Program{};
+  P->groups = (int)keys.size();
+  for (size_t gi = 0; gi < gorder.size(); ++gi) {
+    Program G;
+    if (!merge_programs(cps, members[gorder[gi]], &G, msg)) return false;
+    const int32_t pj0 = (int32_t)P->pjobs.size(), sj0 = (int32_t)P->sjobs.size();
+    for (MergedLaunch L : G.launches) {
+      L.job0 += L.cls >= 0 ? pj0 : sj0;
+      L.group = (int)gi;
+      P->launches.push_back(L);
+    }
+    P->pjobs.insert(P->pjobs.end(), G.pjobs.begin(), G.pjobs.end());
+    P->plaunch.insert(P->plaunch.end(), G.plaunch.begin(), G.plaunch.end());
+    P->pstart.insert(P->pstart.end(), G.pstart.begin(), G.pstart.end());
+    P->sjobs.insert(P->sjobs.end(), G.sjobs.begin(), G.sjobs.end());
+    P->sstart.insert(P->sstart.end(), G.sstart.begin(), G.sstart.end());
+    P->steps = std::max(P->steps, G.steps);
+    P->jobs += G.jobs;
   }
   return true;
 }

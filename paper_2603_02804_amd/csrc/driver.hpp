@@ -157,8 +157,9 @@ inline qf_status build_plan_core(const Circuit& C, int B, const Tuning& T, PlanC
   if (T.micro > 0) {
     c.mb = std::min(T.micro, B);
   } else {
-    // enough workgroups to fill the device several times, bounded by memory
-    const int want_items = 4096;
+    // enough workgroups to fill the device many times over (short passes are
+    // bound by the tail of each launch otherwise), bounded by memory
+    const int want_items = 16384;
     int m = std::max(1, want_items / c.tiles);
     const size_t budget = size_t(16) << 30;
     const size_t per_sample = SB * (size_t)(c.ckpt + 4);

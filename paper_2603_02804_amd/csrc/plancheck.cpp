@@ -832,7 +832,8 @@ int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, i
     }
     const std::vector<int> order = batch_order(cores);
     Program pf, pb;
-    if (!merge_programs(fwd, order, &pf, &msg) || !merge_programs(bwd, order, &pb, &msg)) {
+    // the groups run one after the other here (a valid order: they share no launch)
+    if (!merge_grouped(fwd, cores, order, &pf, &msg) || !merge_grouped(bwd, cores, order, &pb, &msg)) {
       g_err = msg;
       return QF_ERR_UNSUPPORTED;
     }

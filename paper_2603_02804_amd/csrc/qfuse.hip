@@ -61,7 +61,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_assemble(const AssembleArgs a
 
 template <class Real>
 __global__ __launch_bounds__(kSmallThreads) void k_reduce_grads(const ReduceGArgsT<Real> a) {
-  reduce_grads_body(a, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+  __shared__ double red[kSmallThreads];
+  reduce_grads_body(a, blockIdx.x, threadIdx.x, red);
 }
 
 template <class Real>
@@ -399,10 +400,9 @@ struct GpuExec {
 
   void reduce_grads(int nb, int sample0, const float* Gr, float* dtheta, float* dx, bool accumulate) {
     const ReduceGArgs a = make_reduce_grads_args<float>(c, d.p, nb, sample0, Gr, dtheta, dx, accumulate);
-    const long long total = reduce_grads_items(a);
-    if (total == 0) return;
+    if (a.P == 0 && a.dx_items() == 0) return;
     pb();
-    hipLaunchKernelGGL(k_reduce_grads<float>, dim3(blocks_for(total)), dim3(kSmallThreads), 0, st, a);
+    hipLaunchKernelGGL(k_reduce_grads<float>, dim3((unsigned)reduce_grads_blocks(a)), dim3(kSmallThreads), 0, st, a);
     pe(2);
     check("k_reduce_grads");
   }
@@ -502,10 +502,9 @@ struct GpuExec {
   template <class Real>
   void pg_reduce_grads(int nb, int sample0, const Real* Gr, Real* dtheta, Real* dx, bool accumulate) {
     const ReduceGArgsT<Real> a = make_reduce_grads_args<Real>(c, d.p, nb, sample0, Gr, dtheta, dx, accumulate);
-    const long long total = reduce_grads_items(a);
-    if (total == 0) return;
+    if (a.P == 0 && a.dx_items() == 0) return;
     pb();
-    hipLaunchKernelGGL(k_reduce_grads<Real>, dim3(blocks_for(total)), dim3(kSmallThreads), 0, st, a);
+    hipLaunchKernelGGL(k_reduce_grads<Real>, dim3((unsigned)reduce_grads_blocks(a)), dim3(kSmallThreads), 0, st, a);
     pe(2);
     check("k_reduce_grads");
   }

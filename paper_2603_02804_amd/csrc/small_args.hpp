@@ -56,6 +56,11 @@ struct ReduceGArgsT {
   Real* dtheta;
   Real* dx;
   int nb, sample0, n_angle, P, F, accumulate;
+  // dtheta blocks: each sums cols angles over the micro-batch with kSmallThreads / cols
+  // sample lanes (lane j takes samples j, j + lanes, ...), then a fixed tree over the lanes
+  int cols, th_blocks;
+  // (the dx pointer of a mixed batch is only known at call time: items are counted regardless)
+  long long dx_items() const { return (long long)nb * F; }
 };
 using ReduceGArgs = ReduceGArgsT<float>;
 
@@ -153,11 +158,23 @@ inline ReduceGArgsT<Real> make_reduce_grads_args(const PlanCore& c, const PlanPt
   a.P = c.C.P;
   a.F = c.C.F;
   a.accumulate = accumulate ? 1 : 0;
+  // wide blocks of angles when there are many (coalesced rows of Gr), more sample
+  // lanes per angle when there are few
+  int cols = 1;
+  while (cols < 64 && cols < a.P) cols *= 2;
+  a.cols = cols;
+  a.th_blocks = (a.P + cols - 1) / cols;
   return a;
 }
 
+// Blocks of kSmallThreads threads: th_blocks for dtheta, then one thread per
+// (sample, input) for dx.
 template <class Real>
-inline long long reduce_grads_items(const ReduceGArgsT<Real>& a) { return a.P + (long long)a.nb * a.F; }
+inline long long reduce_grads_blocks(const ReduceGArgsT<Real>& a) {
+  const long long nx = a.dx_items();
+  return (long long)a.th_blocks + (nx + kSmallThreads - 1) / kSmallThreads;
+}
+inline size_t reduce_grads_shmem() { return sizeof(double) * kSmallThreads; }
 
 // ---------------------------------------------------------------- mixed batches
 // Caller buffers of one circuit of a mixed batch, refreshed on every call.

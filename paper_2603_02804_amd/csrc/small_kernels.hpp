@@ -234,24 +234,43 @@ __device__ inline void assemble_body(const AssembleArgs& a, int blk, double* fsu
 }
 
 // theta: sum over the micro-batch and over the gates sharing the angle; x: sum
-// over the gates sharing the input, per sample.  Fixed order.
+// over the gates sharing the input, per sample.  Block blk < th_blocks owns
+// angles [blk * cols, (blk + 1) * cols): thread t takes angle t % cols and sample
+// lane t / cols, sums its samples (lane, lane + lanes, ...) in order, and the
+// lanes are added by a fixed pairwise tree in LDS (red: kSmallThreads doubles), so
+// the result does not depend on scheduling.  The later blocks form dx, one thread
+// per (sample, input).
 template <class Real>
-__device__ inline void reduce_grads_body(const ReduceGArgsT<Real>& a, long long idx) {
-  if (idx < a.P) {
-    const int p = (int)idx;
+__device__ inline void reduce_grads_body(const ReduceGArgsT<Real>& a, int blk, int t, double* red) {
+  if (blk < a.th_blocks) {
+    const int cols = a.cols, lanes = kSmallThreads / cols;
+    const int col = t % cols, lane = t / cols;
+    const int p = blk * cols + col;
     double acc = 0;
-    for (int s = 0; s < a.nb; ++s)
-      for (int i = a.T.th_ref_begin[p]; i < a.T.th_ref_begin[p + 1]; ++i)
-        acc += a.Gr[(long long)s * a.n_angle + a.T.th_refs[i]];
-    a.dtheta[p] = a.accumulate ? a.dtheta[p] + (Real)acc : (Real)acc;
-  } else if (a.dx && idx < a.P + (long long)a.nb * a.F) {
-    const long long j = idx - a.P;
-    const int s = (int)(j / a.F), f = (int)(j - (long long)s * a.F);
-    double acc = 0;
-    for (int i = a.T.in_ref_begin[f]; i < a.T.in_ref_begin[f + 1]; ++i)
-      acc += a.Gr[(long long)s * a.n_angle + a.T.in_refs[i]];
-    a.dx[(long long)(a.sample0 + s) * a.F + f] = (Real)acc;
+    if (p < a.P) {
+      const int r0 = a.T.th_ref_begin[p], r1 = a.T.th_ref_begin[p + 1];
+      for (int s = lane; s < a.nb; s += lanes)
+        for (int i = r0; i < r1; ++i) acc += a.Gr[(long long)s * a.n_angle + a.T.th_refs[i]];
+    }
+    red[t] = acc;
+    __syncthreads();
+    for (int half = lanes / 2; half >= 1; half /= 2) {
+      if (lane < half) red[t] += red[t + half * cols];
+      __syncthreads();
+    }
+    if (lane == 0 && p < a.P) {
+      const double sum = red[col];
+      a.dtheta[p] = a.accumulate ? a.dtheta[p] + (Real)sum : (Real)sum;
+    }
+    return;
   }
+  const long long j = (long long)(blk - a.th_blocks) * kSmallThreads + t;
+  if (!a.dx || j >= (long long)a.nb * a.F) return;
+  const int s = (int)(j / a.F), f = (int)(j - (long long)s * a.F);
+  double acc = 0;
+  for (int i = a.T.in_ref_begin[f]; i < a.T.in_ref_begin[f + 1]; ++i)
+    acc += a.Gr[(long long)s * a.n_angle + a.T.in_refs[i]];
+  a.dx[(long long)(a.sample0 + s) * a.F + f] = (Real)acc;
 }
 
 template <class Real>
