@@ -510,7 +510,8 @@ def bench_mixed(args, dev) -> int:
     dEs = [torch.ones(s, 1, device=dev) for s in samples]
     t0 = time.perf_counter()
     unc = 1 if args.uncompute is None else args.uncompute
-    batch = qfuse.Batch(circs, samples, qfuse.make_tuning(epoch_fill=args.epoch_fill, uncompute=unc))
+    batch = qfuse.Batch(circs, samples, qfuse.make_tuning(epoch_fill=args.epoch_fill, uncompute=unc,
+                                                           fusion_depth=args.fusion_depth))
     t_create = time.perf_counter() - t0
     info = batch.info
     wsb = batch.new_workspace(dev)

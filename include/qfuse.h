@@ -337,9 +337,12 @@ typedef struct {
 /*
  * circuits[i] is simulated for samples[i] >= 1 samples; each gets the plan that
  * qf_plan_create would build (Sec. 3.2-3.4: runs fused into passes,
- * checkpoint segments), and the plans' launch sequences are merged.  tuning
- * (may be NULL) applies to every circuit's plan; mode must be 0 (fused);
- * mem_save may be set.  Errors: QF_ERR_INVALID_ARG (NULL or empty arrays,
+ * checkpoint segments), and the plans' launch sequences are merged: circuits
+ * of one tile shape share launches, and the shapes run on concurrent streams.
+ * tuning (may be NULL) applies to every circuit's plan, with batch defaults for
+ * its zero fields (epoch_fill -1, i.e. no end-of-pass epoch waits; fusion_depth
+ * 12 for circuits larger than one tile), since every pass costs a merged step;
+ * mode must be 0 (fused); mem_save may be set.  Errors: QF_ERR_INVALID_ARG (NULL or empty arrays,
  * samples < 1), QF_ERR_UNSUPPORTED (mode != 0, X or Y factors in an
  * observable, or any qf_plan_create refusal, named by circuit index),
  * QF_ERR_OOM.  The plans and merged tables live on the current HIP device.

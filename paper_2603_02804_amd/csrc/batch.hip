@@ -25,9 +25,19 @@
 
 namespace qf {
 
-// Last job whose first block is <= blockIdx.x (jobs sorted by first block).
-__device__ __forceinline__ int find_job(const int32_t* start, int n_jobs) {
-  const int b = blockIdx.x;
+// Workgroups are dealt to the 8 XCDs of the device round-robin by block index.
+// The merged launches renumber them so that each XCD runs one contiguous range
+// of blocks, i.e. whole jobs of a few circuits: each XCD's L2 (and its CUs'
+// scalar caches) then hold the tables of those circuits only.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, n = gridDim.x;
+  const int q = n / kXcds, r = n % kXcds, x = b % kXcds;
+  return x * q + min(x, r) + b / kXcds;
+}
+
+// Last job whose first block is <= b (jobs sorted by first block).
+__device__ __forceinline__ int find_job(const int32_t* start, int n_jobs, int b) {
   int lo = 0, hi = n_jobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -45,7 +55,8 @@ __device__ __forceinline__ T* rebase(T* p, char* ws) {
 template <int R, int NT, bool BWD>
 __global__ __launch_bounds__(NT, (pass_min_waves<R, BWD>())) void k_pass_multi(const PassJob* jobs, const int32_t* start, int n_jobs,
                                                    char* ws, const CircPtrs* ptrs) {
-  const int j = find_job(start, n_jobs);
+  const int b = xcd_block();
+  const int j = find_job(start, n_jobs, b);
   KArgs A = cld(&jobs[j].A);
   const int circ = cld(&jobs[j].circ);
   A.coef_sh = rebase(A.coef_sh, ws);
@@ -60,16 +71,17 @@ __global__ __launch_bounds__(NT, (pass_min_waves<R, BWD>())) void k_pass_multi(c
   A.partF = rebase(A.partF, ws);
   A.partE = rebase(A.partE, ws);
   A.dE = cld(&ptrs[circ].dE);
-  pass_body<R, NT, BWD>(A, (int)blockIdx.x - cld(start + j));
+  pass_body<R, NT, BWD>(A, b - cld(start + j));
 }
 
 __global__ __launch_bounds__(kSmallThreads) void k_small_multi(const SmallJob* jobs, const int32_t* start,
                                                                int n_jobs, char* ws, const CircPtrs* ptrs) {
   extern __shared__ double fsum[];
-  const int j = find_job(start, n_jobs);
+  const int b = xcd_block();
+  const int j = find_job(start, n_jobs, b);
   const int kind = cld(&jobs[j].kind);
   const CircPtrs P = cld(&ptrs[cld(&jobs[j].circ)]);
-  const int blk = (int)blockIdx.x - cld(start + j);
+  const int blk = b - cld(start + j);
   const long long idx = (long long)blk * blockDim.x + threadIdx.x;
   switch (kind) {
     case SJ_COEF: {
@@ -293,10 +305,10 @@ qf_status qf_batch_create(const qf_circuit* const* circuits, const int32_t* samp
   std::memset(&bt, 0, sizeof(bt));
   bt.store_ckpt = -1;
   if (tuning) bt = *tuning;
-  if (bt.epoch_fill == 0) bt.epoch_fill = kBatchEpochFill;
   for (int i = 0; i < n_circuits; ++i) {
     qf_plan* p = nullptr;
-    const qf_status st = qf_plan_create(circuits[i], samples[i], &bt, &p);
+    const qf_tuning ct = batch_plan_tuning(bt, circuits[i]->c.n);
+    const qf_status st = qf_plan_create(circuits[i], samples[i], &ct, &p);
     if (st != QF_OK) {
       const std::string m = "circuit " + std::to_string(i) + ": " + qf_last_error();
       destroy_batch(b);

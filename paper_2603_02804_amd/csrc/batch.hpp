@@ -28,6 +28,21 @@ namespace qf {
 // pass per step and extra passes cost whole steps.
 constexpr int kBatchEpochFill = -1;
 
+// Default fusion depth of the plans of a mixed batch whose circuits exceed one
+// tile (tuning fusion_depth 0): deeper than a single plan's, since every pass
+// costs a merged step (smaller circuits keep the single-plan default).
+constexpr int kBatchFusionDepth = 12;
+
+// The tuning of one circuit's plan in a mixed batch: the batch's tuning, whose
+// zero fields take the batch defaults above.
+inline qf_tuning batch_plan_tuning(const qf_tuning& bt, int n_qubits) {
+  qf_tuning t = bt;
+  if (t.epoch_fill == 0) t.epoch_fill = kBatchEpochFill;
+  const int k = t.tile_qubits > 0 ? t.tile_qubits : kDefaultTileQubits;
+  if (t.fusion_depth == 0 && n_qubits > k) t.fusion_depth = kBatchFusionDepth;
+  return t;
+}
+
 // Compiled pass kernel variants: register qubits R in 1..5, NT in {64,128,256},
 // forward or backward.
 constexpr int kPassClasses = 30;

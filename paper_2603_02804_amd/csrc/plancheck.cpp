@@ -795,12 +795,10 @@ int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, i
                   float* const* dtheta, float* const* dx, int64_t* stats) {
   try {
     std::string msg;
-    Tuning T;
-    if (tuning) {
-      T.mode = tuning->mode; T.k = tuning->tile_qubits; T.R = tuning->reg_qubits; T.fusion = tuning->fusion_depth;
-      T.ckpt = tuning->ckpt_interval; T.micro = tuning->micro_batch; T.store = tuning->store_ckpt; T.memsave = tuning->mem_save; T.fill = tuning->epoch_fill; T.uncompute = tuning->uncompute;
-    }
-    if (T.fill == 0) T.fill = kBatchEpochFill;
+    qf_tuning bt;
+    std::memset(&bt, 0, sizeof(bt));
+    bt.store_ckpt = -1;
+    if (tuning) bt = *tuning;
     std::vector<std::unique_ptr<PlanCore>> pcs;
     std::vector<const PlanCore*> cores;
     std::vector<PlanPtrs> ptrs;
@@ -809,6 +807,11 @@ int qfc_batch_run(const qf_circuit_desc* const* descs, const int32_t* samples, i
       if (st != QF_OK) { g_err = msg; return st; }
       Circuit C;
       circuit_from_desc(descs[i], &C);
+      const qf_tuning ct = batch_plan_tuning(bt, C.n);
+      Tuning T;
+      T.mode = ct.mode; T.k = ct.tile_qubits; T.R = ct.reg_qubits; T.fusion = ct.fusion_depth;
+      T.ckpt = ct.ckpt_interval; T.micro = ct.micro_batch; T.store = ct.store_ckpt; T.memsave = ct.mem_save;
+      T.fill = ct.epoch_fill; T.uncompute = ct.uncompute;
       pcs.emplace_back(new PlanCore);
       st = build_plan_core(C, samples[i], T, pcs.back().get(), &msg);
       if (st != QF_OK) { g_err = msg; return st; }

@@ -36,7 +36,11 @@ def test_batch_replay_equals_single(case):
                                            **case["tuning"])
     for i, c in enumerate(ws):
         single = dict(case["tuning"])
-        single.setdefault("epoch_fill", -1)   # the default of a batch's plans
+        # the defaults of a batch's plans: no end-of-pass epoch waits, and fusion depth 12
+        # for circuits larger than one tile
+        single.setdefault("epoch_fill", -1)
+        if c.n_qubits > single.get("tile_qubits", 12):
+            single.setdefault("fusion_depth", 12)
         E1, dth1, dx1 = plancheck.run(c.n_qubits, c.gates, c.theta, c.x, zm, dEs[i], **single)
         np.testing.assert_array_equal(Es[i], E1)
         np.testing.assert_array_equal(dth[i], dth1)

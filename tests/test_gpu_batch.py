@@ -29,7 +29,12 @@ def _setup(ws, dev, seed=0):
 def _single(circs, ws, thetas, xs, dEs, dev, **tun):
     out = []
     for c, w, t, x, d in zip(circs, ws, thetas, xs, dEs):
-        plan = qfuse.Plan(c, w.x.shape[0], qfuse.make_tuning(epoch_fill=-1, **tun))   # a batch's default
+        # a batch's defaults: no end-of-pass epoch waits, fusion depth 12 beyond one tile
+        t_c = dict(tun)
+        t_c.setdefault("epoch_fill", -1)
+        if w.n_qubits > t_c.get("tile_qubits", 12):
+            t_c.setdefault("fusion_depth", 12)
+        plan = qfuse.Plan(c, w.x.shape[0], qfuse.make_tuning(**t_c))
         wsb = plan.new_workspace(dev)
         E = plan.forward(t, x, wsb)
         dth, dx = plan.backward(t, x, d, wsb)
