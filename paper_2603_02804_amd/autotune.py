@@ -33,9 +33,9 @@ import numpy as np
 TUNED_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_configs.json")
 
 # (tile qubits, register qubits) shapes with compiled kernels
-TILE_SHAPES = ((12, 4), (13, 5), (11, 4))
+TILE_SHAPES = ((12, 4), (13, 5), (11, 4), (10, 4))
 FUSION_DEPTHS = (4, 6, 8, 10, 12, 16)
-MICRO_BATCHES = (8, 16, 32, 64, 128, 256, 512)
+MICRO_BATCHES = (8, 16, 32, 64, 128, 256, 512, 1024)
 # end-of-pass epoch thresholds tried besides the default (every partial epoch waits): none waits, half
 EPOCH_FILLS = (-1, 2)
 
