@@ -223,6 +223,9 @@ def autotune(n_qubits: int, gates, n_params: int, n_inputs: int, z_masks: Sequen
                                                       micro_batch=out["micro_batch"],
                                                       epoch_fill=out["epoch_fill"]))
     passes = probe.info.fused_passes
+    del probe
+    # the candidates' workspaces stay in torch's cache otherwise and shrink the free memory
+    torch.cuda.empty_cache()
     free = torch.cuda.mem_get_info()[0]
     budget = budget_bytes if budget_bytes is not None else int(0.85 * free)
     if out["uncompute"]:
