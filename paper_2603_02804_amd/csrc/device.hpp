@@ -159,6 +159,61 @@ __device__ __forceinline__ void func3_all(const float2 (&a)[1 << R], const float
   }
 }
 
+// Im<l|X_q|a> and Im<l|Y_q|a> over the pairs along register bit J (the terms
+// couple the two amplitudes of a pair: eight fused multiply-adds per pair).
+template <int R, int J>
+__device__ __forceinline__ void func_xy(const float2 (&a)[1 << R], const float2 (&l)[1 << R], float& fx, float& fy) {
+#pragma unroll
+  for (int i = 0; i < (1 << R); ++i) {
+    if (i & (1 << J)) continue;
+    constexpr int m = 1 << J;
+    const float2 p0 = a[i], p1 = a[i | m], l0 = l[i], l1 = l[i | m];
+    fx = fmaf(l0.x, p1.y, fx); fx = fmaf(-l0.y, p1.x, fx); fx = fmaf(l1.x, p0.y, fx); fx = fmaf(-l1.y, p0.x, fx);
+    fy = fmaf(l1.x, p0.x, fy); fy = fmaf(l1.y, p0.y, fy); fy = fmaf(-l0.x, p1.x, fy); fy = fmaf(-l0.y, p1.y, fy);
+  }
+}
+
+// Im<l|Z_q|a> of every register bit q.  Z is diagonal, so with u_i = Im(conj(l_i) a_i)
+// per slot the functional of bit J is sum_i (-1)^(bit J of i) u_i, i.e. twice the sum
+// over the slots with bit J clear minus the sum over all slots.  The slots are added
+// pairwise along bit 0, then along bit 1, and so on; before the additions along bit J
+// the entries with bit J clear are the even ones.  62 instructions for R = 4, against
+// 128 fused multiply-adds when each bit sums its pairs on its own.
+template <int R>
+__device__ __forceinline__ void func_z_all(const float2 (&a)[1 << R], const float2 (&l)[1 << R], float (&z)[R]) {
+  // level 0 streamed from the slots: u of each pair, the even-slot sum and the pair sums
+  float w[(1 << R) / 2];
+  float ev[R];
+#pragma unroll
+  for (int k = 0; k < (1 << R) / 2; ++k) {
+    const float u0 = fmaf(l[2 * k].x, a[2 * k].y, -(l[2 * k].y * a[2 * k].x));
+    const float u1 = fmaf(l[2 * k + 1].x, a[2 * k + 1].y, -(l[2 * k + 1].y * a[2 * k + 1].x));
+    ev[0] = k == 0 ? u0 : ev[0] + u0;
+    w[k] = u0 + u1;
+  }
+#pragma unroll
+  for (int j = 1; j < R; ++j) {
+    const int n = (1 << R) >> j;
+    float e = w[0];
+#pragma unroll
+    for (int m = 2; m < n; m += 2) e += w[m];
+    ev[j] = e;
+#pragma unroll
+    for (int m = 0; m < n / 2; ++m) w[m] = w[2 * m] + w[2 * m + 1];
+  }
+  // w[0]: the sum over all slots
+#pragma unroll
+  for (int j = 0; j < R; ++j) z[j] = fmaf(2.f, ev[j], -w[0]);
+}
+
+template <int R, int J = 0>
+__device__ __forceinline__ void func_xy_all(const float2 (&a)[1 << R], const float2 (&l)[1 << R], float (&v)[3 * R]) {
+  if constexpr (J < R) {
+    func_xy<R, J>(a, l, v[3 * J], v[3 * J + 1]);
+    func_xy_all<R, J + 1>(a, l, v);
+  }
+}
+
 template <int NA>
 __device__ __forceinline__ void scale_all(float2 (&a)[NA], float2 p) {
 #pragma unroll
@@ -235,6 +290,45 @@ __device__ __forceinline__ int wave_sum_index(int lane) {
   return ((lane >> 5) & 1) * 8 + ((lane >> 4) & 1) * 4 + (lane & 1) * 2 + ((lane >> 1) & 1);
 }
 __device__ __forceinline__ bool wave_sum_writer(int lane) { return (lane & 12) == 0; }
+
+// Reduce-scatter of 12 per-lane values (the three functionals of four register
+// bits) over a wave of 64 lanes.  Lane bit 5 pairs v[i] with v[i + 6] and lane bit
+// 4 pairs v[i] with v[i + 3] (one permlane swap and one add per pair); lane bit 0
+// splits v[0] from v[1] and sums v[2] whole, lane bit 1 splits those two results,
+// and lane bits 3 and 2 are summed whole.  Afterwards every lane holds the wave sum
+// of value wave_sum_index12(lane); 27 instructions, against 43 for the 16-value
+// reduction padded with zeros.
+__device__ __forceinline__ float wave_reduce12(float (&v)[12], int lane) {
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 6]), false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[i + 3]), false, false);
+    v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  {
+    const bool hi = (lane & 1) != 0;
+    v[0] = sum_split(v[0], v[1], dpp_mov<kDppQuadXor1>(v[0]), dpp_mov<kDppQuadXor1>(v[1]), hi);
+    v[1] = v[2] + dpp_mov<kDppQuadXor1>(v[2]);
+  }
+  {
+    const bool hi = (lane & 2) != 0;
+    v[0] = sum_split(v[0], v[1], dpp_mov<kDppQuadXor2>(v[0]), dpp_mov<kDppQuadXor2>(v[1]), hi);
+  }
+  v[0] += dpp_mov<kDppRowRor8>(v[0]);
+  v[0] += dpp_mov<kDppRowRor4>(v[0]);
+  return v[0];
+}
+
+// Value whose wave sum lane `lane` holds after wave_reduce12: 3 * e + p with e =
+// lane bits 5,4 (the register bit) and p = 2 where lane bit 1 is set, else lane
+// bit 0 (the Pauli); the writer lanes (bits 2 and 3 clear, not both of bits 0 and
+// 1 set) hold each value once.
+__device__ __forceinline__ int wave_sum_pauli12(int lane) { return (lane & 2) ? 2 : (lane & 1); }
+__device__ __forceinline__ bool wave_sum_writer12(int lane) { return (lane & 12) == 0 && (lane & 3) != 3; }
 
 __device__ __forceinline__ const float* run_coef(const KArgs& A, int ref, int sample) {
   return ref >= 0 ? A.coef_sh + 8 * (size_t)ref : A.coef_ps + 8 * ((size_t)sample * A.n_ps + (-1 - ref));
@@ -446,27 +540,53 @@ struct PassCtx {
       int sl[R];
 #pragma unroll
       for (int j = 0; j < R; ++j) sl[j] = cld(&fe[j].slot);
-      float v[16];
+      // part[wave][slot][Pauli], through an LDS-typed pointer
+      __attribute__((address_space(3))) float* part = (__attribute__((address_space(3))) float*)qf_pass_part;
+      if constexpr (R == 4) {
+        float v[12];
+        float z[R];
+        func_z_all<R>(a, l, z);
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = 0.f;
-      func3_all<R>(a, l, v);
-      // lanes beyond a small tile hold copies of in-tile elements: no share (a
-      // uniform test first, so that full tiles skip the per-lane selects)
-      if (A.tb < ThreadBitsOf<NT>::value && !active) {
+        for (int j = 0; j < R; ++j) {
+          v[3 * j] = v[3 * j + 1] = 0.f;
+          v[3 * j + 2] = z[j];
+        }
+        func_xy_all<R>(a, l, v);
+        // lanes beyond a small tile hold copies of in-tile elements: no share
+        // (workgroups of more than 64 threads always cover whole tiles)
+        if constexpr (NT == 64) {
+          if (A.tb < 6 && !active) {
+#pragma unroll
+            for (int i = 0; i < 12; ++i) v[i] = 0.f;
+          }
+        }
+        const float sum = wave_reduce12(v, lane);
+        // the slots of bits 0,1 and 2,3 as 16-bit halves (no run: 0xffff); a
+        // lane picks its half with lane bits 5 and 4, which give its register bit
+        const uint32_t slots01 = ((uint32_t)sl[0] & 0xffffu) | ((uint32_t)sl[1] << 16);
+        const uint32_t slots23 = ((uint32_t)sl[2] & 0xffffu) | ((uint32_t)sl[3] << 16);
+        const uint32_t slot = (((lane & 32) ? slots23 : slots01) >> (lane & 16)) & 0xffffu;
+        if (wave_sum_writer12(lane) && slot != 0xffffu)
+          part[wave * 3 * n_slots + 3 * (int)slot + wave_sum_pauli12(lane)] = sum;
+      } else {
+        float v[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) v[i] = 0.f;
-      }
-      const float sum = wave_reduce16(v, lane);
-      const int idx = wave_sum_index(lane);
-      if (wave_sum_writer(lane) && idx < 3 * R) {
-        const int e = idx / 3, pq = idx - 3 * e;
-        int slot = sl[0];
+        func3_all<R>(a, l, v);
+        if constexpr (NT == 64) {
+          if (A.tb < 6 && !active) {
 #pragma unroll
-        for (int j = 1; j < R; ++j) slot = (e == j) ? sl[j] : slot;
-        if (slot >= 0) {
-          // through an LDS-typed pointer
-          __attribute__((address_space(3))) float* part = (__attribute__((address_space(3))) float*)qf_pass_part;
-          part[wave * 3 * n_slots + 3 * slot + pq] = sum;
+            for (int i = 0; i < 16; ++i) v[i] = 0.f;
+          }
+        }
+        const float sum = wave_reduce16(v, lane);
+        const int idx = wave_sum_index(lane);
+        if (wave_sum_writer(lane) && idx < 3 * R) {
+          const int e = idx / 3, pq = idx - 3 * e;
+          int slot = sl[0];
+#pragma unroll
+          for (int j = 1; j < R; ++j) slot = (e == j) ? sl[j] : slot;
+          if (slot >= 0) part[wave * 3 * n_slots + 3 * slot + pq] = sum;
         }
       }
     }
