@@ -396,6 +396,9 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
   S.R = R;
   S.thread_bits = tb;
   S.active = 1 << tb;
+  // a workgroup is one wave for tiles of up to 64 threads, else exactly the tile's
+  // threads: the adjoint pass drops idle lanes' functionals only in 64-thread
+  // workgroups, so wider ones must never hold idle lanes
   S.NT = std::max(64, S.active);
   S.tiles_log2 = n - k;
   S.fusion = F;
@@ -529,7 +532,10 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
   };
   std::vector<int> all(n);
   std::iota(all.begin(), all.end(), 0);
-  const int ncore = std::min(4, k);
+  // core: the qubits at the lowest memory bits, local in consecutive passes so that
+  // the passes' loads and stores stay coalesced; a tile that does not hold the
+  // whole state keeps at least one position for the qubits it brings in
+  const int ncore = n <= k ? std::min(4, k) : std::min(4, k - 1);
   std::vector<int> in_map(n), local;
   std::iota(in_map.begin(), in_map.end(), 0);
   if (n <= k) {

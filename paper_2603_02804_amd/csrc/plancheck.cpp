@@ -777,10 +777,10 @@ int qfc_stats(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tunin
   PlanCore pc;
   st = build_plan_core(C, batch, T, &pc, &msg);
   if (st != QF_OK) { g_err = msg; return st; }
-  int64_t v[14] = {pc.P, pc.n_seg, pc.ckpt, pc.mb, pc.S.n_perm, pc.S.n_u2, pc.S.n_cz, (int64_t)pc.S.layouts.size(),
+  int64_t v[16] = {pc.P, pc.n_seg, pc.ckpt, pc.mb, pc.S.n_perm, pc.S.n_u2, pc.S.n_cz, (int64_t)pc.S.layouts.size(),
                    (int64_t)pc.S.runs.size(), pc.S.k, pc.S.R, (int64_t)pc.ws_bytes, pc.S.n_diag_thread,
-                   pc.S.n_diag_amp};
-  for (int i = 0; i < n_out && i < 14; ++i) out[i] = v[i];
+                   pc.S.n_diag_amp, pc.S.NT, pc.S.thread_bits};
+  for (int i = 0; i < n_out && i < 16; ++i) out[i] = v[i];
   return 0;
 }
 

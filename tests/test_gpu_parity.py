@@ -98,6 +98,8 @@ def test_single_tile(orc, n, L, rots, B, tun):
     (15, 4, ("RY", "RZ"), 2, {"store_ckpt": 0, "micro_batch": 1}),
     (16, 3, ("RX", "RY", "RZ"), 2, {"fusion_depth": 8}),
     (14, 6, ("RY", "RZ"), 2, {"fusion_depth": 12}),   # epochs with up to 3 register-bit phases
+    (7, 3, ("RX", "RY", "RZ"), 2, {"tile_qubits": 3, "reg_qubits": 2, "fusion_depth": 2}),   # tiles of a few qubits
+    (8, 3, ("RY", "RZ"), 3, {"tile_qubits": 4, "reg_qubits": 4}),
 ])
 def test_multi_tile(orc, n, L, rots, B, tun):
     gates, theta, x = hea_case(n, L, rots, B)

@@ -64,6 +64,16 @@ def test_hea_programs(orc, n, L, rots, B, tun):
     check(orc, n, gates, theta, x, obs, **tun)
 
 
+@pytest.mark.parametrize("k,R", [(1, 1), (2, 1), (2, 2), (3, 2), (4, 3), (4, 4), (5, 4)])
+def test_small_tiles(orc, k, R):
+    """Tiles of a few qubits on a wider register (each pass brings in at least one
+    new qubit next to the ones kept at the lowest memory bits) against the oracle."""
+    n, L, B = 7, 3, 2
+    gates = hea_gates(n, L, ("RX", "RY", "RZ"))
+    theta, x, _ = draw_inputs(31, L * 3 * n, B, n)
+    check(orc, n, gates, theta, x, [0, 3, n - 1], tile_qubits=k, reg_qubits=R, fusion_depth=2)
+
+
 @pytest.mark.parametrize("tun", [{}, {"tile_qubits": 8, "reg_qubits": 3, "fusion_depth": 2}, {"mode": 1}])
 def test_general_gate_list(orc, tun):
     rng = np.random.default_rng(5)
@@ -105,6 +115,20 @@ def test_schedule_shape_at_benchmark_sizes():
     assert st["runs"] == 20 * 1000          # encoding merged into layer 1
     assert st["u2"] == st["runs"]           # every run applied exactly once
     assert st["passes"] < 1000              # more than one layer per pass on average
+
+
+@pytest.mark.parametrize("n", [3, 6, 9, 10, 11, 12, 13, 16])
+def test_wide_workgroups_cover_whole_tiles(n):
+    """Workgroups of more than one wave hold exactly the tile's threads (the adjoint
+    pass drops the functionals of idle lanes only in 64-thread workgroups)."""
+    g = hea_gates(n, 2, ("RY", "RZ"))
+    for k in range(1, min(n, 13) + 1):
+        for R in range(1, min(k, 5) + 1):
+            if k - R > 8:
+                continue
+            st = pc.stats(n, g, 2 * 2 * n, n, [1], 4, tile_qubits=k, reg_qubits=R)
+            assert st["threads"] in (64, 1 << st["thread_bits"]), (n, k, R, st)
+            assert st["threads"] >= 1 << st["thread_bits"]
 
 
 @pytest.mark.parametrize("fill", [-1, 1, 2, 0])
