@@ -28,6 +28,16 @@ def random_tuning(rng, n, batch):
                 ckpt_interval=int(rng.integers(0, 4)), micro_batch=int(rng.integers(0, batch + 1)))
 
 
+def random_tuning_wide(rng, n, batch):
+    """Execution choices for 10..16 qubits that the pass kernels support (at most 256
+    threads per tile): default, 10..13 tile qubits with 4 or 5 register qubits."""
+    k = int(rng.choice([0, 10, 11, 12, 13]))
+    R = int(rng.choice([0, 4, 5])) if k != 13 else 5
+    return dict(tile_qubits=min(k, n), reg_qubits=R, fusion_depth=int(rng.integers(0, 13)),
+                epoch_fill=int(rng.choice([-1, 0, 2, 4])), uncompute=int(rng.integers(0, 2)),
+                ckpt_interval=int(rng.integers(0, 4)), micro_batch=int(rng.integers(0, batch + 1)))
+
+
 def random_batch_tuning(rng):
     return dict(fusion_depth=int(rng.integers(0, 7)), epoch_fill=int(rng.choice([-1, 0, 2])),
                 uncompute=int(rng.integers(0, 2)), tile_qubits=int(rng.choice([0, 0, 5, 6, 8])))

@@ -11,7 +11,7 @@ torch = pytest.importorskip("torch")
 from oracle.oracle import Oracle  # noqa: E402
 from paper_2603_02804_amd import qfuse  # noqa: E402
 from paper_2603_02804_amd.workloads import z_observables  # noqa: E402
-from random_cases import close, random_batch_tuning, random_circuit, random_tuning  # noqa: E402
+from random_cases import close, random_batch_tuning, random_circuit, random_tuning, random_tuning_wide  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -28,6 +28,31 @@ def test_random_plan_gpu(orc, seed):
     rng = np.random.default_rng(1000 + seed)
     n, gates, theta, x, obs = random_circuit(rng, seed)
     tun = random_tuning(rng, n, x.shape[0])
+    xm, zm = z_observables(obs)
+    dE = rng.normal(size=(x.shape[0], len(obs))).astype(np.float32)
+    print(f"seed {seed}: n={n} batch={x.shape[0]} tuning={tun}", flush=True)
+    circ = qfuse.Circuit(n, gates, len(theta), n, zm)
+    plan = qfuse.Plan(circ, x.shape[0], qfuse.make_tuning(**tun))
+    ws = plan.new_workspace(dev)
+    th = torch.tensor(theta, device=dev)
+    xx = torch.tensor(x, device=dev)
+    E = plan.forward(th, xx, ws)
+    dth, dx = plan.backward(th, xx, torch.tensor(dE, device=dev), ws)
+    torch.cuda.synchronize()
+    got = (E.cpu().numpy(), dth.cpu().numpy(), dx.cpu().numpy())
+    assert close(*got, orc.backward(n, gates, theta, x, xm, zm, dE)), (n, tun)
+
+
+@pytest.mark.timeout(120)
+@pytest.mark.parametrize("seed", range(30))
+def test_random_wide_plan_gpu(orc, seed):
+    """10..16 qubits: several tiles, swaps to local, random supported tile shapes."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(9000 + seed)
+    n = 0
+    while n < 10:
+        n, gates, theta, x, obs = random_circuit(rng, seed, max_n=16)
+    tun = random_tuning_wide(rng, n, x.shape[0])
     xm, zm = z_observables(obs)
     dE = rng.normal(size=(x.shape[0], len(obs))).astype(np.float32)
     print(f"seed {seed}: n={n} batch={x.shape[0]} tuning={tun}", flush=True)

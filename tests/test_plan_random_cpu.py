@@ -11,7 +11,7 @@ import pytest
 import plancheck as pc
 from oracle.oracle import Oracle
 from paper_2603_02804_amd.workloads import z_observables
-from random_cases import close, random_batch_tuning, random_circuit, random_tuning
+from random_cases import close, random_batch_tuning, random_circuit, random_tuning, random_tuning_wide
 
 
 @pytest.fixture(scope="module")
@@ -24,6 +24,19 @@ def test_random_plan(orc, seed):
     rng = np.random.default_rng(1000 + seed)
     n, gates, theta, x, obs = random_circuit(rng, seed)
     tun = random_tuning(rng, n, x.shape[0])
+    xm, zm = z_observables(obs)
+    dE = rng.normal(size=(x.shape[0], len(obs))).astype(np.float32)
+    E, dth, dx = pc.run(n, gates, theta, x, zm, dE, **tun)
+    assert close(E, dth, dx, orc.backward(n, gates, theta, x, xm, zm, dE)), (n, tun)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_random_wide_plan(orc, seed):
+    rng = np.random.default_rng(9000 + seed)
+    n = 0
+    while n < 10:
+        n, gates, theta, x, obs = random_circuit(rng, seed, max_n=16)
+    tun = random_tuning_wide(rng, n, x.shape[0])
     xm, zm = z_observables(obs)
     dE = rng.normal(size=(x.shape[0], len(obs))).astype(np.float32)
     E, dth, dx = pc.run(n, gates, theta, x, zm, dE, **tun)
