@@ -184,17 +184,38 @@ LayoutRec make_layout(const std::vector<int>& reg_pos, const std::vector<int>& t
   return L;
 }
 
-// Orders thread positions so that lanes 0..3 take distinct residues mod 4 of
-// their tile positions (conflict-free 64-bit LDS accesses with the swizzle).
+// Orders thread positions so that the lanes of one LDS cycle reach distinct
+// bank slots: lanes 0..4 take positions whose swizzled elements are independent
+// on element bits 0..4 (32 lanes of 8-byte accesses in 256 bytes), lanes 0..3 if
+// possible also on bits 0..3 (16 lanes in 128 bytes).  Greedy in tile order; the
+// other positions follow in tile order.
 std::vector<int> order_thread_positions(std::vector<int> free_pos, int tb) {
   std::vector<int> out;
-  for (int r = 0; r < 4 && (int)out.size() < std::min(tb, 4); ++r) {
-    for (size_t i = 0; i < free_pos.size(); ++i)
-      if ((free_pos[i] & 3) == r) {
-        out.push_back(free_pos[i]);
-        free_pos.erase(free_pos.begin() + i);
-        break;
-      }
+  uint32_t b4[4] = {0, 0, 0, 0}, b5[5] = {0, 0, 0, 0, 0};   // reduced vectors by leading bit
+  auto reduce = [](const uint32_t* basis, int bits, uint32_t v) {
+    v &= (1u << bits) - 1u;
+    for (int b = bits - 1; b >= 0; --b)
+      if (((v >> b) & 1u) && basis[b]) v ^= basis[b];
+    return v;
+  };
+  auto insert = [&](uint32_t* basis, int bits, uint32_t v) {
+    v = reduce(basis, bits, v);
+    for (int b = bits - 1; b >= 0; --b)
+      if ((v >> b) & 1u) { basis[b] = v; return; }
+  };
+  while ((int)out.size() < std::min(tb, 5)) {
+    int pick = -1, best = 0;
+    for (size_t i = 0; i < free_pos.size() && best < 2; ++i) {
+      const uint32_t e = lds_swizzle(1u << free_pos[i]);
+      const int score = reduce(b5, 5, e) == 0 ? 0 : (out.size() < 4 && reduce(b4, 4, e) != 0) || out.size() >= 4 ? 2 : 1;
+      if (score > best) { best = score; pick = (int)i; }
+    }
+    if (pick < 0) break;
+    const uint32_t e = lds_swizzle(1u << free_pos[pick]);
+    insert(b4, 4, e);
+    insert(b5, 5, e);
+    out.push_back(free_pos[pick]);
+    free_pos.erase(free_pos.begin() + pick);
   }
   for (int p : free_pos) out.push_back(p);
   out.resize(tb);

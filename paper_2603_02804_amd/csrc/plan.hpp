@@ -89,11 +89,17 @@ bool build_schedule(const Circuit& c, const Tuning& t, Schedule* s, std::string*
 // Runs and gate tables only, one run per rotation gate (the per-gate baseline).
 void build_gate_runs(const Circuit& c, Schedule* s);
 
-// Swizzled LDS element index of tile index i.
+// Swizzled LDS element index of tile index i: tile bits 5..11 each add a
+// pattern to element bits 0..4 (the 32 eight-byte bank slots that one LDS cycle
+// serves), chosen so that almost every set of 8 tile positions (a 256-thread
+// layout's thread positions) holds 5 positions independent on those bits: the
+// lanes 0..4 of every layout then reach 32 distinct bank slots.
 inline uint32_t lds_swizzle(uint32_t i) {
+  constexpr uint32_t fold[7] = {13u, 21u, 25u, 19u, 31u, 22u, 7u};
   uint32_t f = 0;
-  for (uint32_t h = i >> kSwizzleBits; h; h >>= kSwizzleBits) f ^= h;
-  return i ^ (f & ((1u << kSwizzleBits) - 1));
+  for (int b = 0; b < 7; ++b)
+    if ((i >> (5 + b)) & 1u) f ^= fold[b];
+  return i ^ f;
 }
 
 }  // namespace qf

@@ -18,7 +18,6 @@ constexpr int kMaxR = 5;           // register-resident qubits per lane
 constexpr int kMaxThreadBits = 8;  // up to 256 threads per workgroup
 constexpr int kMaxTileQubits = kMaxR + kMaxThreadBits;
 constexpr int kMaxQubits = 30;
-constexpr int kSwizzleBits = 4;    // LDS XOR swizzle folds 4-bit chunks
 constexpr int kDefaultTileQubits = 12;
 constexpr int kDefaultRegQubits = 4;
 
