@@ -345,7 +345,17 @@ static void fuse_epochs(Schedule* Sp) {
         continue;
       }
       if (j < end && S.ops[j].kind == OP_CZA) { e.cza = S.ops[j].a; e.cza_layout = S.ops[j].b; ++j; }
-      if (j < end && (S.ops[j].kind == OP_RY || S.ops[j].kind == OP_RYG)) take_ry(S.ops[j++], &e);
+      if (j < end && (S.ops[j].kind == OP_RY || S.ops[j].kind == OP_RYG)) {
+        take_ry(S.ops[j++], &e);
+      } else {
+        // no runs (the exchange into the store layout at the end of a pass): its ops
+        // stay single, so the epoch loop never applies an empty run group (as the
+        // adjoint program, which fuses from its runs, leaves them too)
+        S.phas.resize(e.pha_first);
+        for (int q = i; q < j; ++q) out.push_back(S.ops[q]);
+        i = j;
+        continue;
+      }
       emit(e);
       i = j;
     }
