@@ -825,8 +825,21 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
         if (!placed[q]) { out_map[q] = m++; placed[q] = 1; }
     }
     for (int i = 0; i < pr.n_nonlocal; ++i) pr.nl_out[i] = (uint8_t)out_map[pr.nl_log[i]];
-    int io_out = io_layout(out_map);
-    S.ops.push_back({OP_PERM, cur, io_out, 0, 0, 0, 0, 0});
+    // the store layout keeps the last epoch's register and thread positions, with
+    // the memory bits of the next pass's order: the tile is stored where it is,
+    // without an exchange into memory order (the L2 cache merges the lanes' writes
+    // into whole lines; the counted HBM traffic is unchanged)
+    int io_out = (int)S.layouts.size();
+    {
+      LayoutRec L = S.layouts[cur];
+      for (int j = 0; j < R; ++j) L.mem_reg[j] = 1u << out_map[L.reg_qubit[j]];
+      for (int b = 0; b < tb; ++b) {
+        int q = 0;
+        while (!((L.log_thr[b] >> q) & 1u)) ++q;
+        L.mem_thr[b] = 1u << out_map[q];
+      }
+      S.layouts.push_back(L);
+    }
     cur = io_out;
     set_regs();
     if (!last) apply_free();
