@@ -697,7 +697,10 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
     };
 
     while (true) {
-      apply_free();
+      // while the pass holds only its LOAD (INIT0), the first exchange is folded
+      // into it: the tile is loaded straight into the first epoch's layout
+      const bool at_load = S.ops.size() == (size_t)fop_begin + 1;
+      if (!at_load) apply_free();
       std::vector<int> cands;
       for (int q : local)
         if (has_run(q) && pass_runs[q] < F && gap_released(q)) cands.push_back(q);
@@ -731,11 +734,19 @@ bool build_schedule(const Circuit& C, const Tuning& T, Schedule* Sp, std::string
           if (std::find(reg.begin(), reg.end(), p) == reg.end()) free_pos.push_back(p);
         std::vector<int> thr = order_thread_positions(free_pos, tb);
         int id = (int)S.layouts.size();
-        S.layouts.push_back(make_layout(reg, thr, local, nullptr, R));
-        S.ops.push_back({OP_PERM, cur, id, 0, 0, 0, 0, 0});
-        S.n_perm++;
+        S.layouts.push_back(make_layout(reg, thr, local, at_load ? &in_map : nullptr, R));
+        if (at_load) {
+          // the LOAD (INIT0) reads the pass's memory order into this layout: its
+          // lanes' reads scatter over the tile's lines, which the caches absorb
+          S.ops[fop_begin].a = id;
+        } else {
+          S.ops.push_back({OP_PERM, cur, id, 0, 0, 0, 0, 0});
+          S.n_perm++;
+        }
         cur = id;
         set_regs();
+        apply_free();
+      } else if (at_load) {
         apply_free();
       }
       // items that still block the chosen runs touch register bits: per amplitude

@@ -147,7 +147,7 @@ def test_epoch_fill_trades_epochs_for_passes():
     off = pc.stats(20, g, 3600, 0, [1], 8, epoch_fill=-1)
     on = pc.stats(20, g, 3600, 0, [1], 8)
     assert on["u2"] == off["u2"] == 20 * 60
-    assert on["perm"] < 0.95 * off["perm"]
+    assert on["perm"] < 0.97 * off["perm"]   # (exchanges within passes: loads and stores need none)
     assert on["passes"] < off["passes"]
     g = hea_gates(20, 60, ("RX", "RY", "RZ"))
     off = pc.stats(20, g, 3600, 20, [1], 8, epoch_fill=-1)
