@@ -763,6 +763,46 @@ int qfc_run(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tuning,
 }
 
 // Schedule statistics: passes, segments, ops, layout count.
+// Worst LDS bank-slot sharing of a plan's tile exchanges: for every PERM (single
+// or inside an epoch, forward and backward programs), both its write and its
+// read layout, every wave and register slot, the largest number of distinct
+// elements that the 32 lanes of one LDS cycle (8-byte accesses: 256 bytes from
+// 64 banks) place in one 8-byte bank slot.  1 means conflict-free; lanes that
+// read the same element share it.
+static int64_t lds_bank_degree(const Schedule& S) {
+  const int NA = 1 << S.R, tb = S.thread_bits;
+  auto side = [&](const LayoutRec& L) {
+    int64_t worst = 1;
+    for (int w = 0; w < std::max(1, S.NT / 64); ++w)
+      for (int jj = 0; jj < NA; ++jj)
+        for (int half = 0; half < 2; ++half) {
+          std::vector<std::vector<uint32_t>> slot(32);
+          for (int ln = half * 32; ln < half * 32 + 32; ++ln) {
+            const int t = (w * 64 + ln) & ((1 << tb) - 1);   // lanes above the tile repeat in-tile ones
+            uint32_t v = 0;
+            for (int b = 0; b < tb; ++b)
+              if ((t >> b) & 1) v ^= L.lds_thr[b];
+            const uint32_t e = (v ^ reg_index(L.lds_reg, jj)) / kLdsElemBytes;
+            std::vector<uint32_t>& sl = slot[e & 31u];
+            if (std::find(sl.begin(), sl.end(), e) == sl.end()) sl.push_back(e);
+            worst = std::max<int64_t>(worst, (int64_t)sl.size());
+          }
+        }
+    return worst;
+  };
+  int64_t worst = 1;
+  auto perm = [&](int from, int to) {
+    worst = std::max(worst, side(S.layouts[from]));
+    worst = std::max(worst, side(S.layouts[to]));
+  };
+  for (const Op& o : S.ops) {
+    if (o.kind == OP_PERM) perm(o.a, o.b);
+    if (o.kind == OP_EPOCH)
+      for (int e = o.a; e < o.a + o.b; ++e) perm(S.epochs[e].perm_from, S.epochs[e].perm_to);
+  }
+  return worst;
+}
+
 int qfc_stats(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tuning, int64_t* out, int n_out) {
   std::string msg;
   qf_status st = validate_circuit(desc, &msg);
@@ -777,10 +817,10 @@ int qfc_stats(const qf_circuit_desc* desc, int32_t batch, const qf_tuning* tunin
   PlanCore pc;
   st = build_plan_core(C, batch, T, &pc, &msg);
   if (st != QF_OK) { g_err = msg; return st; }
-  int64_t v[16] = {pc.P, pc.n_seg, pc.ckpt, pc.mb, pc.S.n_perm, pc.S.n_u2, pc.S.n_cz, (int64_t)pc.S.layouts.size(),
+  int64_t v[17] = {pc.P, pc.n_seg, pc.ckpt, pc.mb, pc.S.n_perm, pc.S.n_u2, pc.S.n_cz, (int64_t)pc.S.layouts.size(),
                    (int64_t)pc.S.runs.size(), pc.S.k, pc.S.R, (int64_t)pc.ws_bytes, pc.S.n_diag_thread,
-                   pc.S.n_diag_amp, pc.S.NT, pc.S.thread_bits};
-  for (int i = 0; i < n_out && i < 16; ++i) out[i] = v[i];
+                   pc.S.n_diag_amp, pc.S.NT, pc.S.thread_bits, pc.per_gate ? 1 : lds_bank_degree(pc.S)};
+  for (int i = 0; i < n_out && i < 17; ++i) out[i] = v[i];
   return 0;
 }
 

@@ -82,12 +82,12 @@ def run(n, gates, theta, x, zmask, dE=None, xmask=None, psi0=None, **tuning):
 def stats(n, gates, n_params, n_inputs, zmask, batch, **tuning):
     d, keep = _desc(n, gates, n_params, n_inputs, zmask)
     t = make_tuning(**tuning)
-    out = (ctypes.c_int64 * 16)()
-    rc = lib().qfc_stats(ctypes.byref(d), batch, ctypes.byref(t), out, 16)
+    out = (ctypes.c_int64 * 17)()
+    rc = lib().qfc_stats(ctypes.byref(d), batch, ctypes.byref(t), out, 17)
     if rc != 0:
         raise RuntimeError(f"qfc_stats: {rc} {lib().qfc_last_error().decode()}")
     keys = ["passes", "segments", "ckpt", "micro_batch", "perm", "u2", "cz", "layouts", "runs", "k", "R", "ws_bytes",
-            "diag_thread", "diag_amp", "threads", "thread_bits"]
+            "diag_thread", "diag_amp", "threads", "thread_bits", "lds_bank_degree"]
     return dict(zip(keys, list(out)))
 
 

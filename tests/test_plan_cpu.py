@@ -192,3 +192,30 @@ def test_uncompute_workspace_holds_no_segment_states():
     unc = pc.stats(16, g, 40 * 48, 16, [1], 8, ckpt_interval=4, micro_batch=4, uncompute=1)
     SB = 8 << 16
     assert rec["ws_bytes"] - unc["ws_bytes"] >= 3 * 4 * SB   # (ckpt - 1) x micro-batch stored outputs
+
+
+@pytest.mark.parametrize("n,L,rots,tun", [
+    (20, 64, ("RX", "RY", "RZ"), {"fusion_depth": 4, "uncompute": 1}),
+    (20, 64, ("RX", "RY", "RZ"), {"fusion_depth": 8}),
+    (16, 40, ("RX", "RY", "RZ"), {"fusion_depth": 16, "uncompute": 1}),
+    (13, 30, ("RY", "RZ"), {"fusion_depth": 12, "uncompute": 1, "epoch_fill": -1}),
+    (18, 30, ("RY", "RZ"), {"fusion_depth": 12, "uncompute": 1, "epoch_fill": -1}),
+    (12, 30, ("RY", "RZ"), {"fusion_depth": 12}),
+    (11, 20, ("RY", "RZ"), {"fusion_depth": 12}),
+])
+def test_exchanges_free_of_lds_bank_conflicts(n, L, rots, tun):
+    """Tiles of 11 and 12 qubits: in every exchange layout the 32 lanes of one LDS
+    cycle place their 8-byte elements in 32 distinct bank slots (the swizzle folds
+    tile bits 5 and up onto element bits 0..4 and the planner orders lanes 0..4 to be
+    independent there)."""
+    g = hea_gates(n, L, rots)
+    st = pc.stats(n, g, len(rots) * n * L, n, [1], 4, **tun)
+    assert st["k"] >= 11 and st["lds_bank_degree"] == 1, st
+
+
+def test_ten_qubit_tiles_share_at_most_two_elements_per_bank_slot():
+    """Tiles of 10 qubits (64 threads) cannot be conflict-free for every choice of
+    register positions under one fixed fold set; they stay at two elements per slot."""
+    g = hea_gates(10, 20, ("RY", "RZ"))
+    st = pc.stats(10, g, 400, 10, [1], 4, fusion_depth=12)
+    assert st["k"] == 10 and st["lds_bank_degree"] <= 2, st
