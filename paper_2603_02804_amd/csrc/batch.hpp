@@ -15,6 +15,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -67,6 +68,7 @@ struct CircProgram {
   std::vector<PassJob> pj;
   std::vector<PassLaunch> pl;       // the driver's view of each pass job (host checks)
   std::vector<uint32_t> pblocks, pshmem;
+  std::vector<uint32_t> pcost;      // work per workgroup of each pass job (its runs, plus the tile load and store)
   std::vector<SmallJob> sj;
   std::vector<uint32_t> sblocks, sshmem;
 };
@@ -119,6 +121,9 @@ struct RecordExec {
     out.pl.push_back(L);
     out.pblocks.push_back(pass_blocks(c, L.nb));
     out.pshmem.push_back((uint32_t)pass_shmem(c, L.bwd));
+    const int p = L.pass;
+    const int runs = p + 1 < (int)c.S.pass_run_begin.size() ? c.S.pass_run_begin[p + 1] - c.S.pass_run_begin[p] : 0;
+    out.pcost.push_back((uint32_t)(runs + 8));
   }
   // circuits with X / Y observables are rejected at batch creation
   void pauli_expect(const float*, int64_t, int, float*) { failed = true; }
@@ -164,7 +169,40 @@ struct Program {
   int groups = 1;                   // independent launch sequences (one per tile shape)
 };
 
-// Merges the circuits' sequences; within a launch, jobs follow `order`.
+// Job order of one merged pass launch.  Each XCD runs one contiguous eighth of
+// the blocks, so the order spreads the work evenly over them: jobs are taken
+// costliest first, each time the one that keeps the running sum of work closest
+// to (average work per block) x (running sum of blocks).  Every XCD then ends its
+// range at about the same time, while each job stays contiguous (its circuit's
+// tables on one XCD).
+inline void balance_pass_jobs(const std::vector<CircProgram>& cps, std::vector<std::pair<int, int>>* jobs) {
+  std::vector<std::pair<int, int>> rem = *jobs;
+  auto blocks = [&](const std::pair<int, int>& j) { return (double)cps[j.first].pblocks[j.second]; };
+  auto cost = [&](const std::pair<int, int>& j) { return (double)cps[j.first].pcost[j.second]; };
+  std::stable_sort(rem.begin(), rem.end(), [&](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+    return cost(a) > cost(b);
+  });
+  double tb = 0, tw = 0;
+  for (auto& j : rem) { tb += blocks(j); tw += blocks(j) * cost(j); }
+  const double avg = tb > 0 ? tw / tb : 0;
+  jobs->clear();
+  double cb = 0, cw = 0;
+  while (!rem.empty()) {
+    size_t best = 0;
+    double bd = -1;
+    for (size_t i = 0; i < rem.size(); ++i) {
+      const double d = std::fabs(cw + blocks(rem[i]) * cost(rem[i]) - avg * (cb + blocks(rem[i])));
+      if (bd < 0 || d < bd) { bd = d; best = i; }
+    }
+    cb += blocks(rem[best]);
+    cw += blocks(rem[best]) * cost(rem[best]);
+    jobs->push_back(rem[best]);
+    rem.erase(rem.begin() + best);
+  }
+}
+
+// Merges the circuits' sequences; within a small-kernel launch, jobs follow
+// `order`; within a pass launch, `balance_pass_jobs` orders them.
 inline bool merge_programs(const std::vector<CircProgram>& cps, const std::vector<int>& order, Program* P,
                            std::string* msg) {
   *P = Program{};
@@ -192,6 +230,7 @@ inline bool merge_programs(const std::vector<CircProgram>& cps, const std::vecto
       L.shmem = 0;
       uint64_t blocks = 0;
       if (L.cls >= 0) {
+        balance_pass_jobs(cps, &by[k]);
         L.job0 = (int32_t)P->pjobs.size();
         for (auto& cj : by[k]) {
           const CircProgram& cp = cps[cj.first];
@@ -270,7 +309,8 @@ inline bool merge_grouped(const std::vector<CircProgram>& cps, const std::vector
   return true;
 }
 
-// Job order inside a merged launch: heavier circuits (amplitudes x passes x
+// Circuit order of the merged small-kernel launches (and the starting order of
+// the pass launches' balancing): heavier circuits (amplitudes x passes x
 // samples) first, so that their workgroups are dispatched first.
 inline std::vector<int> batch_order(const std::vector<const PlanCore*>& cores) {
   std::vector<int> order(cores.size());
