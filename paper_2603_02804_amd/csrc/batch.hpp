@@ -29,6 +29,10 @@ namespace qf {
 // pass per step and extra passes cost whole steps.
 constexpr int kBatchEpochFill = -1;
 
+// The heaviest tile-shape group of a mixed batch is merged as two halves that run
+// on two streams (see merge_grouped).
+constexpr bool kSplitHeaviestGroup = true;
+
 // Default fusion depth of the plans of a mixed batch whose circuits exceed one
 // tile (tuning fusion_depth 0): deeper than a single plan's, since every pass
 // costs a merged step (smaller circuits keep the single-plan default).
@@ -265,8 +269,9 @@ inline bool merge_programs(const std::vector<CircProgram>& cps, const std::vecto
 
 // Circuits grouped by tile shape (the pass kernel variant their plan uses), each
 // group merged on its own: the groups share no launch, so the caller can run
-// them concurrently.  Groups are ordered by work, heaviest first; `order` keeps
-// its order inside each group.  The job tables of all groups are concatenated.
+// them concurrently.  The heaviest group is split in two halves of equal weight.
+// Groups are ordered by work, heaviest first; `order` keeps its order inside
+// each group.  The job tables of all groups are concatenated.
 inline bool merge_grouped(const std::vector<CircProgram>& cps, const std::vector<const PlanCore*>& cores,
                           const std::vector<int>& order, Program* P, std::string* msg) {
   std::vector<int> keys;
@@ -283,6 +288,26 @@ inline bool merge_grouped(const std::vector<CircProgram>& cps, const std::vector
     }
     members[g].push_back(c);
     weight[g] += (double)cores[c]->amps * cores[c]->P * cores[c]->B;
+  }
+  // the heaviest group in two halves of equal weight on streams of their own: each
+  // half's launches fill the workgroup slots that the other's launch tails leave
+  if (kSplitHeaviestGroup && !members.empty()) {
+    size_t h = 0;
+    for (size_t g = 1; g < members.size(); ++g)
+      if (weight[g] > weight[h]) h = g;
+    if (members[h].size() >= 2) {
+      std::vector<int> a, b;
+      double wa = 0, wb = 0;
+      for (int c : members[h]) {   // heaviest first (`order`), each to the lighter half
+        const double w = (double)cores[c]->amps * cores[c]->P * cores[c]->B;
+        if (wa <= wb) { a.push_back(c); wa += w; } else { b.push_back(c); wb += w; }
+      }
+      members[h] = a;
+      weight[h] = wa;
+      keys.push_back(keys[h]);
+      members.push_back(b);
+      weight.push_back(wb);
+    }
   }
   std::vector<size_t> gorder(keys.size());
   for (size_t g = 0; g < gorder.size(); ++g) gorder[g] = g;
