@@ -29,9 +29,9 @@ namespace qf {
 // pass per step and extra passes cost whole steps.
 constexpr int kBatchEpochFill = -1;
 
-// The heaviest tile-shape group of a mixed batch is merged as two halves that run
-// on two streams (see merge_grouped).
-constexpr bool kSplitHeaviestGroup = true;
+// The heaviest tile-shape group of a mixed batch is merged as this many parts of
+// equal weight that run on streams of their own (see merge_grouped).
+constexpr int kHeaviestGroupParts = 2;
 
 // Default fusion depth of the plans of a mixed batch whose circuits exceed one
 // tile (tuning fusion_depth 0): deeper than a single plan's, since every pass
@@ -269,7 +269,7 @@ inline bool merge_programs(const std::vector<CircProgram>& cps, const std::vecto
 
 // Circuits grouped by tile shape (the pass kernel variant their plan uses), each
 // group merged on its own: the groups share no launch, so the caller can run
-// them concurrently.  The heaviest group is split in two halves of equal weight.
+// them concurrently.  The heaviest group is split in parts of equal weight.
 // Groups are ordered by work, heaviest first; `order` keeps its order inside
 // each group.  The job tables of all groups are concatenated.
 inline bool merge_grouped(const std::vector<CircProgram>& cps, const std::vector<const PlanCore*>& cores,
@@ -289,24 +289,30 @@ inline bool merge_grouped(const std::vector<CircProgram>& cps, const std::vector
     members[g].push_back(c);
     weight[g] += (double)cores[c]->amps * cores[c]->P * cores[c]->B;
   }
-  // the heaviest group in two halves of equal weight on streams of their own: each
-  // half's launches fill the workgroup slots that the other's launch tails leave
-  if (kSplitHeaviestGroup && !members.empty()) {
+  // the heaviest group in parts of equal weight on streams of their own: each
+  // part's launches fill the workgroup slots that the others' launch tails leave
+  if (kHeaviestGroupParts > 1 && !members.empty()) {
     size_t h = 0;
     for (size_t g = 1; g < members.size(); ++g)
       if (weight[g] > weight[h]) h = g;
-    if (members[h].size() >= 2) {
-      std::vector<int> a, b;
-      double wa = 0, wb = 0;
-      for (int c : members[h]) {   // heaviest first (`order`), each to the lighter half
-        const double w = (double)cores[c]->amps * cores[c]->P * cores[c]->B;
-        if (wa <= wb) { a.push_back(c); wa += w; } else { b.push_back(c); wb += w; }
+    const int parts = (int)std::min<size_t>(kHeaviestGroupParts, members[h].size());
+    if (parts > 1) {
+      std::vector<std::vector<int>> pm(parts);
+      std::vector<double> pw(parts, 0.0);
+      for (int c : members[h]) {   // heaviest first (`order`), each to the lightest part
+        int m = 0;
+        for (int i = 1; i < parts; ++i)
+          if (pw[i] < pw[m]) m = i;
+        pm[m].push_back(c);
+        pw[m] += (double)cores[c]->amps * cores[c]->P * cores[c]->B;
       }
-      members[h] = a;
-      weight[h] = wa;
-      keys.push_back(keys[h]);
-      members.push_back(b);
-      weight.push_back(wb);
+      members[h] = pm[0];
+      weight[h] = pw[0];
+      for (int i = 1; i < parts; ++i) {
+        keys.push_back(keys[h]);
+        members.push_back(pm[i]);
+        weight.push_back(pw[i]);
+      }
     }
   }
   std::vector<size_t> gorder(keys.size());
