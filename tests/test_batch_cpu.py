@@ -36,9 +36,9 @@ def test_batch_replay_equals_single(case):
                                            **case["tuning"])
     for i, c in enumerate(ws):
         single = dict(case["tuning"])
-        # the defaults of a batch's plans: no end-of-pass epoch waits, and fusion depth 12
-        # for circuits larger than one tile
-        single.setdefault("epoch_fill", -1)
+        # the defaults of a batch's plans: end-of-pass epochs of fewer than 2 runs wait
+        # for the next pass, and fusion depth 12 for circuits larger than one tile
+        single.setdefault("epoch_fill", 2)
         if c.n_qubits > single.get("tile_qubits", 12):
             single.setdefault("fusion_depth", 12)
         E1, dth1, dx1 = plancheck.run(c.n_qubits, c.gates, c.theta, c.x, zm, dEs[i], **single)

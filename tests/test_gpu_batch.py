@@ -29,9 +29,10 @@ def _setup(ws, dev, seed=0):
 def _single(circs, ws, thetas, xs, dEs, dev, **tun):
     out = []
     for c, w, t, x, d in zip(circs, ws, thetas, xs, dEs):
-        # a batch's defaults: no end-of-pass epoch waits, fusion depth 12 beyond one tile
+        # a batch's defaults: end-of-pass epochs of fewer than 2 runs wait, fusion depth 12
+        # beyond one tile
         t_c = dict(tun)
-        t_c.setdefault("epoch_fill", -1)
+        t_c.setdefault("epoch_fill", 2)
         if w.n_qubits > t_c.get("tile_qubits", 12):
             t_c.setdefault("fusion_depth", 12)
         plan = qfuse.Plan(c, w.x.shape[0], qfuse.make_tuning(**t_c))
